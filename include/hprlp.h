@@ -1,0 +1,180 @@
+/*
+ * hprlp.h -- C ABI of the MI355X (gfx950) HPR-LP library.
+ *
+ * The library solves, on one GPU,
+ *
+ *     min <c, x>  s.t.  A1 x = b1,  A2 x >= b2,  l <= x <= u          (paper, eq. primalLP)
+ *
+ * with the Halpern Peaceman-Rachford method with semi-proximal terms (Algorithm 2 of
+ * "HPR-LP: An implementation of an HPR method for solving linear programming",
+ * arXiv 2408.12179), including its restart rule (Section 3.1), its sigma update
+ * (Section 3.2, Algorithm 3) and its GPU iteration (Section 3.3, eqs. update-z, update-x,
+ * update-y-2).  Every step of the iteration runs in hand-written HIP kernels; the host only
+ * takes the scalar decisions made every `check_every` iterations.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: an hprlp_err; 0 on success, negative on error.  The solve outcome is
+ *     reported separately (hprlp_status).  After an error, hprlp_last_error(handle) (or
+ *     hprlp_last_error(NULL) when no handle exists yet) gives a message.
+ *   - Matrix: CSR of A = [A1; A2] with the m1 equality rows first, then the m2 inequality
+ *     rows.  rowptr: int64[m+1], rowptr[0] = 0, non-decreasing, rowptr[m] = nnz < 2^31;
+ *     colidx: int32[nnz] in [0, n) (order inside a row is free; repeats are rejected);
+ *     val: double[nnz].  All of these are HOST pointers and are copied.
+ *   - Vectors b[m], c[n], l[n], u[n] are host double arrays; l may hold -INFINITY and u
+ *     +INFINITY.  They are copied.
+ *   - Device memory: the library never allocates device memory.  The caller passes one
+ *     device workspace of at least hprlp_workspace_bytes() bytes (256-byte aligned) and keeps
+ *     it alive until hprlp_destroy.  All work is ordered on the caller's HIP stream.
+ *   - Output vectors (x, y, z, iterates) may be host or device pointers; the library detects
+ *     which.  They are always in the ORIGINAL (unscaled) space of the problem as given.
+ *   - Threads: one call at a time per handle; different handles are independent.
+ */
+#ifndef HPRLP_H
+#define HPRLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hprlp_handle hprlp_handle;
+
+typedef enum {
+    HPRLP_OK = 0,
+    HPRLP_EINVAL = -1,       /* null pointer, bad option value, workspace too small      */
+    HPRLP_EDIM = -2,         /* bad sizes, rowptr not monotone, column index out of range */
+    HPRLP_ENONFINITE = -3,   /* NaN anywhere, or an infinite value in A, b or c           */
+    HPRLP_EBOUNDS = -4,      /* l_j > u_j, l_j = +inf or u_j = -inf                       */
+    HPRLP_ENOTLOSSLESS = -5, /* MIXED precision asked but some A value is not FP32-exact  */
+    HPRLP_ENOMEM = -6,       /* host allocation failed                                    */
+    HPRLP_EHIP = -7,         /* a HIP runtime call failed                                 */
+    HPRLP_ESTATE = -8        /* call not valid in the handle's current state              */
+} hprlp_err;
+
+typedef enum {
+    HPRLP_UNSOLVED = 0,
+    HPRLP_OPTIMAL = 1,    /* max(rel_gap, rel_p, rel_d) <= tol (Section 4.1)            */
+    HPRLP_ITER_LIMIT = 2,
+    HPRLP_TIME_LIMIT = 3,
+    HPRLP_NUMERICAL = 4   /* a NaN appeared in the check quantities                     */
+} hprlp_status;
+
+typedef enum { HPRLP_FP64 = 0, HPRLP_MIXED = 1 } hprlp_precision;
+
+typedef struct {
+    double tol;              /* termination tolerance (default 1e-8; Section 4.1)          */
+    long long check_every;   /* restart/termination check period (default 150; Sec. 4.1)  */
+    long long max_iter;      /* default 10^7                                               */
+    double time_limit;       /* seconds, <= 0: none (default 0)                            */
+    double alpha1, alpha2, alpha3; /* restart parameters (default 0.2, 0.6, 0.2; Sec. 4.1) */
+    double sigma0;           /* initial penalty (default 1; Section 4.1)                   */
+    int ruiz_iters;          /* Ruiz passes (default 10; Section 4.1)                      */
+    int pock_chambolle;      /* 1: one diagonal Pock-Chambolle pass, alpha = 1 (default 1) */
+    int normalize_bc;        /* 1: divide b, c by (||b||+1), (||c||+1) (default 1)         */
+    int power_max_iter;      /* power method cap (default 5000)                            */
+    double power_tol;        /* relative change of the Rayleigh quotient (default 1e-10)   */
+    double lambda_override;  /* > 0: use this lambda, skip the power method                */
+    int use_halpern;         /* 1: Halpern averaging (Algorithm 2); 0: plain PR iteration  */
+    int use_restart;         /* 1: restart criteria of Section 3.1                         */
+    int sigma_update;        /* 1: SigmaUpdate (Algorithm 3); 0: sigma stays sigma0        */
+    int precision;           /* HPRLP_FP64 or HPRLP_MIXED (FP32 until tol_switch)          */
+    double tol_switch;       /* MIXED: switch to FP64 once rel. KKT <= this (default 1e-5) */
+    int tile_nnz;            /* schedule: nonzeros staged per tile (0 = default)           */
+    int tile_rows;           /* schedule: rows per tile (0 = default)                      */
+    int short_max;           /* schedule: longest row kept in tiles (0 = default)          */
+    int split_len;           /* schedule: rows longer than this are split (0 = default)    */
+    int chunk_nnz;           /* schedule: nonzeros per split chunk (0 = default)           */
+    int profile;             /* 1: time every pass launch with HIP events (stats)          */
+    int verbose;             /* 1: one log line per check on stderr                        */
+} hprlp_options;
+
+typedef struct {
+    long long iters;         /* iterations done (the k of Algorithm 2)                     */
+    long long restarts;      /* outer loops started after the first (the r)               */
+    long long iters_fp32;    /* MIXED: iterations done in the FP32 phase                   */
+    int status;              /* hprlp_status of the last solve                             */
+    int power_iters;
+    double sigma, lambda;
+    double rel_p, rel_d, rel_gap;  /* of the returned w_bar, original data (Section 4.1)  */
+    double pobj, dobj;
+    double beta_b, beta_c;   /* b/c normalisation factors                                  */
+    double t_power_ms;       /* power method (counted in the solve time, Section 4.1)      */
+    double t_solve_ms;       /* whole solve incl. power method; excludes create            */
+    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration in the final phase  */
+    double col_pass_ms, row_pass_ms;   /* profile=1: summed kernel time of each pass        */
+    long long col_pass_launches, row_pass_launches;
+    long long n_checks;
+} hprlp_stats_t;
+
+/* Iterates that hprlp_get_iterate can return (original space unless noted). */
+typedef enum {
+    HPRLP_XBAR = 0,  /* x_bar of the last checked iteration (the returned primal)         */
+    HPRLP_YBAR = 1,  /* y_bar of the last checked iteration (the returned dual, length m) */
+    HPRLP_ZBAR = 2,  /* z_bar of the last checked iteration (eq. update-z)                */
+    HPRLP_XCUR = 3,  /* current iterate x^{r,t} after the last Halpern step               */
+    HPRLP_YCUR = 4,  /* current iterate y^{r,t}                                           */
+    HPRLP_DROW = 5,  /* row scaling D_r (length m; A~ = D_r A D_c)                        */
+    HPRLP_DCOL = 6   /* column scaling D_c (length n)                                     */
+} hprlp_iterate;
+
+/* Fill *opt with the defaults listed above (the paper's settings, Section 4.1). */
+void hprlp_default_options(hprlp_options *opt);
+
+/* Upper bound of the device workspace needed for a problem with m1 + m2 rows, n columns and
+ * nnz nonzeros under *opt (NULL: defaults).  Writes *bytes.  Host only; EDIM on bad sizes. */
+int hprlp_workspace_bytes(int64_t m1, int64_t m2, int64_t n, int64_t nnz,
+                          const hprlp_options *opt, size_t *bytes);
+
+/* Validate and preprocess one LP (eq. primalLP) and upload it into d_workspace:
+ *   - validation (see hprlp_err), done before any HIP call;
+ *   - preconditioning on the host: 10 Ruiz passes, one Pock-Chambolle alpha=1 pass,
+ *     b/c normalisation (Section 4.1, "Presolve and preconditioning");
+ *   - CSR(A) and a stored CSR(A^T), so neither sparse product needs atomics;
+ *   - the row-length tile schedules of both matrices.
+ * m1 >= 0 equality rows, m2 >= 0 inequality rows, m1 + m2 >= 1, n >= 1, nnz >= 1 (A != 0,
+ * Section 1).  stream: a hipStream_t (NULL = default stream).  On success *out owns host
+ * metadata only; the workspace stays owned by the caller. */
+int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
+                 const int64_t *rowptr, const int32_t *colidx, const double *val,
+                 const double *b, const double *c, const double *l, const double *u,
+                 const hprlp_options *opt, void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Run Algorithm 2 from the origin (Section 4.1) until the relative KKT residual of w_bar
+ * is <= tol at a check, or a limit is hit.  lambda = lambda_1(A~ A~^T) by the power
+ * method unless overridden (T1 = lambda I - A~ A~^T, Section 3.2).  Writes the returned
+ * w_bar = (x, y, z) in the original space (x: n, y: m, z: n; any may be NULL) and *status.
+ * The call blocks until the result is ready. */
+int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int *status);
+
+/* Statistics of the last solve. */
+int hprlp_stats(const hprlp_handle *h, hprlp_stats_t *out);
+
+/* Copy one iterate (hprlp_iterate) of the last solve into out (host or device pointer,
+ * length n or m). */
+int hprlp_get_iterate(const hprlp_handle *h, int which, double *out);
+
+/* Check trace of the last solve: one row of 18 doubles per check, columns
+ * (k, t, r, sigma, merit, merit0, merit_prev, rel_p, rel_d, rel_gap, pobj, dobj,
+ *  Delta_x, Delta_y, err_p, err_d, restarted, sigma_next).  Copies at most cap rows into
+ * out (host) and writes the total row count to *n_rows. */
+int hprlp_get_trace(const hprlp_handle *h, double *out, long long cap, long long *n_rows);
+
+/* Time the two iteration passes on the current state: `reps` launches of the column pass
+ * (x-step over A~^T) and of the row pass (y-step over A~), each bracketed by HIP events on
+ * the handle's stream.  Writes the mean duration of one launch in milliseconds.  The state
+ * is advanced by these launches (call after a solve, not before one). */
+int hprlp_time_passes(hprlp_handle *h, int reps, double *col_ms, double *row_ms);
+
+/* Human-readable message of the last error on this handle (or of the last failed create
+ * on this thread when h is NULL).  Never NULL. */
+const char *hprlp_last_error(const hprlp_handle *h);
+
+/* Release the handle's host resources (the workspace remains the caller's). */
+void hprlp_destroy(hprlp_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPRLP_H */

@@ -196,11 +196,8 @@ def _certificate(rng, A_rowptr, A_col, A_val, m1, m2, n, l, u, boxed_tie="thirds
 
 
 def _csr_matvec(rowptr, col, val, x, m):
-    prod = val * x[col]
-    out = np.add.reduceat(prod, rowptr[:-1]) if len(prod) else np.zeros(m)
-    out = np.asarray(out, dtype=np.float64)
-    out[np.diff(rowptr) == 0] = 0.0  # reduceat quirk for empty rows
-    return out
+    row_of = np.repeat(np.arange(m), np.diff(rowptr))
+    return np.bincount(row_of, weights=val * x[col], minlength=m).astype(np.float64)
 
 
 def _csr_rmatvec(rowptr, col, val, y, n):

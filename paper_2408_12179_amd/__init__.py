@@ -1,0 +1,10 @@
+"""MI355X-native HPR-LP: the HPR iteration for linear programming on gfx950.
+
+The solver lives in ``libhprlp.so`` (C ABI in ``include/hprlp.h``); ``hprlp`` is its thin
+Python binding.
+"""
+from .hprlp import (FP64, MIXED, HPRLPError, Solution, Solver, default_options, load,
+                    workspace_bytes)
+
+__all__ = ["FP64", "MIXED", "HPRLPError", "Solution", "Solver", "default_options", "load",
+           "workspace_bytes"]

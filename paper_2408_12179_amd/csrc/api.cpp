@@ -1,0 +1,930 @@
+// C ABI and host driver of the HPR-LP library (Algorithm 2 of the paper).
+//
+// The iteration runs entirely in the HIP kernels (kernels.hip); the host launches them and,
+// every check_every iterations (Section 4.1), reads back a dozen reduced FP64 scalars to take
+// the termination, restart (Section 3.1) and sigma (Section 3.2, Algorithm 3) decisions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hprlp_internal.h"
+#include "hprlp_setup.h"
+
+using namespace hprlp;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum TraceCol {
+    TR_K, TR_T, TR_R, TR_SIGMA, TR_MERIT, TR_MERIT0, TR_MERIT_PREV, TR_REL_P, TR_REL_D,
+    TR_REL_GAP, TR_POBJ, TR_DOBJ, TR_DX, TR_DY, TR_ERR_P, TR_ERR_D, TR_RESTART,
+    TR_SIGMA_NEW, TR_NCOL
+};
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Bump allocator over the caller's workspace.
+struct Carver {
+    char *base;
+    size_t cap, used = 0;
+    bool dry;  // only count
+    void *take(size_t bytes) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + ((bytes + 255) & ~size_t(255));
+        if (dry || used > cap) return nullptr;
+        return base + off;
+    }
+    template <class T> T *arr(size_t n) { return static_cast<T *>(take(n * sizeof(T))); }
+};
+
+}  // namespace
+
+struct hprlp_handle {
+    hprlp_options opt{};
+    int64_t m1 = 0, m2 = 0, m = 0, n = 0, nnz = 0;
+    bool mixed = false;
+    hipStream_t st = nullptr;
+    DevMat A, T;
+    VecSet<double> v64;
+    VecSet<float> v32;
+    CheckData chk;
+    double *ux = nullptr, *uy = nullptr;     // unscaling of x and y (FP64 mode: vectors)
+    double *vg = nullptr, *w = nullptr, *hist = nullptr, *inv_norm = nullptr;
+    double *partsA = nullptr, *partsT = nullptr;
+    double *res = nullptr;                  // [4][kNQ]
+    double *outv = nullptr;                 // staging for outputs (n + m + n)
+    double *pinned = nullptr;               // host pinned staging
+    size_t pinned_len = 0;
+    double beta_b = 1, beta_c = 1, bnorm = 0, cnorm = 0, bsnorm = 0, csnorm = 0;
+    std::vector<double> dr, dc;
+    // solve state
+    int prec = 0;
+    long long t = 0, k = 0, r = 0;
+    double sigma = 1, lambda = 0;
+    bool solved = false;
+    hprlp_stats_t stats{};
+    std::vector<std::array<double, TR_NCOL>> trace;
+    std::vector<hipEvent_t> ev_pool;
+    std::string err;
+};
+
+namespace {
+
+int fail(hprlp_handle *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(h, HPRLP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device memory plan; the same function sizes the workspace (dry run) and carves it.
+struct Plan {
+    int64_t m, n, nnz;
+    bool mixed;
+    int itemsA, itemsT, splitA, splitT, slotsA, slotsT;
+    int power_cap;
+};
+
+void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
+    const size_t m = (size_t)p.m, n = (size_t)p.n, nnz = (size_t)p.nnz;
+    const size_t vs = p.mixed ? sizeof(float) : sizeof(double);
+    DevMat A, T;
+    A.rp = cv.arr<int>(m + 1);
+    A.ci = cv.arr<int>(nnz);
+    A.va = cv.take(nnz * vs);
+    T.rp = cv.arr<int>(n + 1);
+    T.ci = cv.arr<int>(nnz);
+    T.va = cv.take(nnz * vs);
+    A.items = cv.arr<int4>((size_t)std::max(p.itemsA, 1));
+    T.items = cv.arr<int4>((size_t)std::max(p.itemsT, 1));
+    A.splits = cv.arr<int4>((size_t)std::max(p.splitA, 1));
+    T.splits = cv.arr<int4>((size_t)std::max(p.splitT, 1));
+    A.split_part = cv.take(16 * (size_t)std::max(p.slotsA, 1));
+    T.split_part = cv.take(16 * (size_t)std::max(p.slotsT, 1));
+    VecSet<double> d;
+    d.xhat = cv.arr<double>(n); d.x0 = cv.arr<double>(n); d.cd = cv.arr<double>(n);
+    d.ld = cv.arr<double>(n); d.ud = cv.arr<double>(n);
+    d.xbar = cv.arr<double>(n); d.zint = cv.arr<double>(n); d.dx = cv.arr<double>(n);
+    d.y = cv.arr<double>(m); d.y0 = cv.arr<double>(m); d.bd = cv.arr<double>(m);
+    d.ybar = cv.arr<double>(m); d.dy = cv.arr<double>(m);
+    VecSet<float> f;
+    if (p.mixed) {
+        d.sc = cv.arr<double>(n);
+        d.sr = cv.arr<double>(m);
+        f.xhat = cv.arr<float>(n); f.x0 = cv.arr<float>(n); f.cd = cv.arr<float>(n);
+        f.ld = cv.arr<float>(n); f.ud = cv.arr<float>(n); f.sc = cv.arr<float>(n);
+        f.xbar = cv.arr<float>(n); f.zint = cv.arr<float>(n); f.dx = cv.arr<float>(n);
+        f.y = cv.arr<float>(m); f.y0 = cv.arr<float>(m); f.bd = cv.arr<float>(m);
+        f.sr = cv.arr<float>(m); f.ybar = cv.arr<float>(m); f.dy = cv.arr<float>(m);
+    }
+    CheckData c;
+    c.ro = cv.arr<double>(m); c.rs = cv.arr<double>(m); c.ys = cv.arr<double>(m);
+    c.co = cv.arr<double>(n); c.cs = cv.arr<double>(n); c.xs = cv.arr<double>(n);
+    c.lo = cv.arr<double>(n); c.uo = cv.arr<double>(n);
+    double *ux = cv.arr<double>(n), *uy = cv.arr<double>(m);
+    double *vg = cv.arr<double>(m), *w = cv.arr<double>(n);
+    double *hist = cv.arr<double>((size_t)p.power_cap);
+    double *inv_norm = cv.arr<double>(1);
+    double *partsA = cv.arr<double>((size_t)(p.itemsA + p.splitA + 1) * kNQ);
+    double *partsT = cv.arr<double>((size_t)(p.itemsT + p.splitT + 1) * kNQ);
+    double *res = cv.arr<double>(4 * kNQ);
+    double *outv = cv.arr<double>(2 * n + m);
+    if (h) {
+        h->A.rp = A.rp; h->A.ci = A.ci; h->A.va = A.va; h->A.items = A.items;
+        h->A.splits = A.splits; h->A.split_part = A.split_part;
+        h->T.rp = T.rp; h->T.ci = T.ci; h->T.va = T.va; h->T.items = T.items;
+        h->T.splits = T.splits; h->T.split_part = T.split_part;
+        h->v64 = d; h->v32 = f; h->chk = c; h->ux = ux; h->uy = uy; h->vg = vg; h->w = w;
+        h->hist = hist; h->inv_norm = inv_norm; h->partsA = partsA; h->partsT = partsT;
+        h->res = res; h->outv = outv;
+    }
+}
+
+int power_cap(const hprlp_options &o) { return o.power_max_iter + 64; }
+
+size_t plan_bytes(const Plan &p) {
+    Carver cv{nullptr, 0, 0, true};
+    carve(cv, p, nullptr);
+    return cv.used + 256;
+}
+
+// Worst-case item counts of a schedule over `rows` rows (see build_schedule): tiles plus
+// long rows plus split rows are at most `rows`; chunks at most nnz/chunk + split rows.
+Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o) {
+    Plan p;
+    p.m = m; p.n = n; p.nnz = nnz; p.mixed = o.precision == HPRLP_MIXED;
+    const int64_t ch = nnz / o.chunk_nnz + 1;
+    p.itemsA = (int)std::min<int64_t>(2 * m + ch, INT32_MAX / 8);
+    p.itemsT = (int)std::min<int64_t>(2 * n + ch, INT32_MAX / 8);
+    p.splitA = (int)std::min<int64_t>(m, nnz / o.split_len + 1);
+    p.splitT = (int)std::min<int64_t>(n, nnz / o.split_len + 1);
+    p.slotsA = (int)ch + p.splitA;
+    p.slotsT = (int)ch + p.splitT;
+    p.power_cap = power_cap(o);
+    return p;
+}
+
+// Host-to-device copy on the handle's stream; returns once the source may be reused.
+template <class T> int upload(hprlp_handle *h, T *dst, const T *src, size_t n) {
+    if (n == 0) return HPRLP_OK;
+    HIPCHK(h, hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return HPRLP_OK;
+}
+
+hipEvent_t pool_event(hprlp_handle *h, size_t idx) {
+    while (h->ev_pool.size() <= idx) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->ev_pool.push_back(e);
+    }
+    return h->ev_pool[idx];
+}
+
+}  // namespace
+
+namespace {
+
+// Device part of hprlp_create: upload matrices (int32 row pointers), schedules, data
+// vectors in the pass coordinates, check multipliers and unscaling vectors.
+int create_device(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
+                  const double *val, const double *b, const double *c, const double *l,
+                  const double *u, const std::vector<int64_t> &rpt,
+                  const std::vector<int32_t> &cit, const std::vector<int32_t> &pos,
+                  const Scaling &sc, const std::vector<double> &bs,
+                  const std::vector<double> &cs) {
+    const hprlp_options &o = h->opt;
+    const int64_t m = h->m, n = h->n, nnz = h->nnz;
+    const double bb = h->beta_b, bc = h->beta_c;
+    int rc;
+    // ---- upload: matrices (int32 row pointers), schedules, data vectors
+    {
+        std::vector<int> rp32((size_t)std::max(m, n) + 1);
+        for (int64_t i = 0; i <= m; ++i) rp32[i] = (int)rowptr[i];
+        if ((rc = upload(h, h->A.rp, rp32.data(), (size_t)m + 1))) return rc;
+        for (int64_t j = 0; j <= n; ++j) rp32[j] = (int)rpt[j];
+        if ((rc = upload(h, h->T.rp, rp32.data(), (size_t)n + 1))) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->st));
+    }
+    if ((rc = upload(h, h->A.ci, colidx, (size_t)nnz))) return rc;
+    if ((rc = upload(h, h->T.ci, cit.data(), (size_t)nnz))) return rc;
+    if (h->mixed) {
+        std::vector<float> f((size_t)nnz);
+        for (int64_t q = 0; q < nnz; ++q) f[q] = (float)val[q];
+        if ((rc = upload(h, (float *)h->A.va, f.data(), (size_t)nnz))) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        for (int64_t q = 0; q < nnz; ++q) f[q] = (float)val[pos[q]];
+        if ((rc = upload(h, (float *)h->T.va, f.data(), (size_t)nnz))) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->st));
+    } else {
+        if ((rc = upload(h, (double *)h->A.va, sc.val.data(), (size_t)nnz))) return rc;
+        std::vector<double> vt((size_t)nnz);
+        for (int64_t q = 0; q < nnz; ++q) vt[q] = sc.val[pos[q]];
+        if ((rc = upload(h, (double *)h->T.va, vt.data(), (size_t)nnz))) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->st));
+    }
+    for (DevMat *M : {&h->A, &h->T}) {
+        if ((rc = upload(h, M->items, M->host.items.data(), M->host.items.size())))
+            return rc;
+        if ((rc = upload(h, M->splits, M->host.splits.data(), M->host.splits.size())))
+            return rc;
+    }
+    // data vectors in the pass coordinates, plus check multipliers and unscaling
+    {
+        std::vector<double> cd(n), ld(n), ud(n), bd(m), co(n), csv(n), xs(n), ro(m), rs(m),
+            ys(m), ux(n), uy(m), sc2, sr2;
+        for (int64_t j = 0; j < n; ++j) {
+            const double d = sc.dc[j];
+            if (h->mixed) {  // x' = D_c x~ = x / beta_b
+                cd[j] = c[j] / bc;
+                ld[j] = l[j] / bb;
+                ud[j] = u[j] / bb;
+                co[j] = bc / (d * d);
+                csv[j] = 1.0 / d;
+                xs[j] = 1.0 / d;
+                ux[j] = bb;
+            } else {         // scaled problem of Section 4.1
+                cd[j] = cs[j];
+                ld[j] = l[j] / d / bb;
+                ud[j] = u[j] / d / bb;
+                co[j] = bc / d;
+                csv[j] = 1.0;
+                xs[j] = 1.0;
+                ux[j] = bb * d;
+            }
+        }
+        for (int64_t i = 0; i < m; ++i) {
+            const double d = sc.dr[i];
+            if (h->mixed) {  // y' = D_r y~ = y / beta_c
+                bd[i] = b[i] / bb;
+                ro[i] = bb;
+                rs[i] = d;
+                ys[i] = 1.0 / d;
+                uy[i] = bc;
+            } else {
+                bd[i] = bs[i];
+                ro[i] = bb / d;
+                rs[i] = 1.0;
+                ys[i] = 1.0;
+                uy[i] = bc * d;
+            }
+        }
+        auto up = [&](double *dst, const std::vector<double> &v) {
+            return upload(h, dst, v.data(), v.size());
+        };
+        if ((rc = up(h->v64.cd, cd)) || (rc = up(h->v64.ld, ld)) || (rc = up(h->v64.ud, ud)) ||
+            (rc = up(h->v64.bd, bd)) || (rc = up(h->chk.co, co)) || (rc = up(h->chk.cs, csv)) ||
+            (rc = up(h->chk.xs, xs)) || (rc = up(h->chk.ro, ro)) || (rc = up(h->chk.rs, rs)) ||
+            (rc = up(h->chk.ys, ys)) || (rc = up(h->ux, ux)) || (rc = up(h->uy, uy)))
+            return rc;
+        if ((rc = upload(h, h->chk.lo, l, (size_t)n)) || (rc = upload(h, h->chk.uo, u, (size_t)n)))
+            return rc;
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        if (h->mixed) {
+            sc2.resize(n);
+            sr2.resize(m);
+            for (int64_t j = 0; j < n; ++j) sc2[j] = sc.dc[j] * sc.dc[j];
+            for (int64_t i = 0; i < m; ++i) sr2[i] = sc.dr[i] * sc.dr[i];
+            if ((rc = up(h->v64.sc, sc2)) || (rc = up(h->v64.sr, sr2))) return rc;
+            auto upf = [&](float *dst, const std::vector<double> &v) {
+                std::vector<float> f(v.size());
+                for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+                int r2 = upload(h, dst, f.data(), f.size());
+                if (r2) return r2;
+                HIPCHK(h, hipStreamSynchronize(h->st));
+                return (int)HPRLP_OK;
+            };
+            if ((rc = upf(h->v32.cd, cd)) || (rc = upf(h->v32.ld, ld)) ||
+                (rc = upf(h->v32.ud, ud)) || (rc = upf(h->v32.bd, bd)) ||
+                (rc = upf(h->v32.sc, sc2)) || (rc = upf(h->v32.sr, sr2)))
+                return rc;
+        }
+        HIPCHK(h, hipStreamSynchronize(h->st));
+    }
+    h->pinned_len = std::max<size_t>(4 * kNQ + 64, (size_t)power_cap(o));
+    HIPCHK(h, hipHostMalloc((void **)&h->pinned, h->pinned_len * sizeof(double), 0));
+    return HPRLP_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+
+extern "C" void hprlp_default_options(hprlp_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->check_every = 150;
+    o->max_iter = 10000000;
+    o->time_limit = 0;
+    o->alpha1 = 0.2;
+    o->alpha2 = 0.6;
+    o->alpha3 = 0.2;
+    o->sigma0 = 1.0;
+    o->ruiz_iters = 10;
+    o->pock_chambolle = 1;
+    o->normalize_bc = 1;
+    o->power_max_iter = 5000;
+    o->power_tol = 1e-10;
+    o->lambda_override = 0;
+    o->use_halpern = 1;
+    o->use_restart = 1;
+    o->sigma_update = 1;
+    o->precision = HPRLP_FP64;
+    o->tol_switch = 1e-5;
+    o->profile = 0;
+    o->verbose = 0;
+    resolve_options(*o);
+}
+
+extern "C" int hprlp_workspace_bytes(int64_t m1, int64_t m2, int64_t n, int64_t nnz,
+                                     const hprlp_options *opt, size_t *bytes) {
+    hprlp_options o;
+    if (opt) o = *opt;
+    else hprlp_default_options(&o);
+    resolve_options(o);
+    if (!bytes) return fail(nullptr, HPRLP_EINVAL, "bytes is null");
+    if (m1 < 0 || m2 < 0 || m1 + m2 < 1 || n < 1 || nnz < 1 || nnz >= (1LL << 31))
+        return fail(nullptr, HPRLP_EDIM, "bad dimensions");
+    std::string err;
+    int rc = validate_options(o, err);
+    if (rc) return fail(nullptr, rc, err);
+    *bytes = plan_bytes(bound_plan(m1 + m2, n, nnz, o));
+    return HPRLP_OK;
+}
+
+extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
+                            const int64_t *rowptr, const int32_t *colidx, const double *val,
+                            const double *b, const double *c, const double *l, const double *u,
+                            const hprlp_options *opt, void *d_workspace, size_t ws_bytes,
+                            void *stream) {
+    if (!out) return fail(nullptr, HPRLP_EINVAL, "out is null");
+    *out = nullptr;
+    hprlp_options o;
+    if (opt) o = *opt;
+    else hprlp_default_options(&o);
+    resolve_options(o);
+    std::string err;
+    int rc = validate_options(o, err);
+    if (rc) return fail(nullptr, rc, err);
+    rc = validate_problem(m1, m2, n, rowptr, colidx, val, b, c, l, u, o, err);
+    if (rc) return fail(nullptr, rc, err);
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255))
+        return fail(nullptr, HPRLP_EINVAL, "workspace must be a non-null 256-byte aligned device pointer");
+
+    const int64_t m = m1 + m2, nnz = rowptr[m];
+    hprlp_handle *h = new (std::nothrow) hprlp_handle();
+    if (!h) return fail(nullptr, HPRLP_ENOMEM, "handle allocation failed");
+    h->opt = o; h->m1 = m1; h->m2 = m2; h->m = m; h->n = n; h->nnz = nnz;
+    h->mixed = o.precision == HPRLP_MIXED;
+    h->st = static_cast<hipStream_t>(stream);
+
+    // ---- host preprocessing
+    std::vector<int64_t> rpt;
+    std::vector<int32_t> cit, pos;
+    transpose(m, n, rowptr, colidx, rpt, cit, pos);
+    Scaling sc;
+    precondition(m, n, rowptr, colidx, rpt, pos, val, o, sc);
+    h->dr = sc.dr;
+    h->dc = sc.dc;
+    std::vector<double> bs((size_t)m), cs((size_t)n);
+    for (int64_t i = 0; i < m; ++i) bs[i] = sc.dr[i] * b[i];
+    for (int64_t j = 0; j < n; ++j) cs[j] = sc.dc[j] * c[j];
+    auto nrm = [](const double *v, int64_t k) {
+        double s = 0;
+        for (int64_t i = 0; i < k; ++i) s += v[i] * v[i];
+        return std::sqrt(s);
+    };
+    h->bnorm = nrm(b, m);
+    h->cnorm = nrm(c, n);
+    h->beta_b = o.normalize_bc ? nrm(bs.data(), m) + 1.0 : 1.0;
+    h->beta_c = o.normalize_bc ? nrm(cs.data(), n) + 1.0 : 1.0;
+    const double bb = h->beta_b, bc = h->beta_c;
+    for (auto &v : bs) v /= bb;
+    for (auto &v : cs) v /= bc;
+    h->bsnorm = nrm(bs.data(), m);
+    h->csnorm = nrm(cs.data(), n);
+
+    ScheduleParams spar{o.tile_nnz, o.tile_rows, o.short_max, o.split_len, o.chunk_nnz};
+    build_schedule(m, rowptr, spar, nullptr, h->A.host);
+    build_schedule(n, rpt.data(), spar, nullptr, h->T.host);
+
+    Plan p = bound_plan(m, n, nnz, o);
+    Plan need = p;
+    need.itemsA = (int)h->A.host.items.size();
+    need.itemsT = (int)h->T.host.items.size();
+    need.splitA = (int)h->A.host.splits.size();
+    need.splitT = (int)h->T.host.splits.size();
+    need.slotsA = h->A.host.n_chunk_slots;
+    need.slotsT = h->T.host.n_chunk_slots;
+    if (plan_bytes(need) > ws_bytes) {
+        delete h;
+        return fail(nullptr, HPRLP_EINVAL, "workspace too small: need " +
+                                               std::to_string(plan_bytes(need)) + " bytes");
+    }
+    Carver cv{static_cast<char *>(d_workspace), ws_bytes, 0, false};
+    carve(cv, need, h);
+    for (DevMat *M : {&h->A, &h->T}) {
+        M->n_items = (int)M->host.items.size();
+        M->n_split = (int)M->host.splits.size();
+        M->tile_nnz = M->host.tile_nnz;
+        M->tile_rows = M->host.tile_rows;
+    }
+    h->A.rows = (int)m;
+    h->T.rows = (int)n;
+
+    rc = create_device(h, rowptr, colidx, val, b, c, l, u, rpt, cit, pos, sc, bs, cs);
+    if (rc) {
+        g_create_error = h->err;
+        hprlp_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return HPRLP_OK;
+}
+namespace {
+
+// Halpern weights of Algorithm 2 at inner counter t (before it is incremented).
+void fill_scalars(const hprlp_handle *h, IterScalars &s) {
+    const double t = (double)h->t;
+    s.sigma = h->sigma;
+    s.lam_sigma = h->lambda * h->sigma;
+    if (h->opt.use_halpern) {
+        s.hx0 = 1.0 / (t + 1.0);
+        s.hx1 = t / (t + 1.0);
+        s.hy0 = 1.0 / (t + 2.0);
+        s.hy1 = (t + 1.0) / (t + 2.0);
+    } else {
+        s.hx0 = 0.0; s.hx1 = 1.0; s.hy0 = 0.0; s.hy1 = 1.0;
+    }
+    s.m1 = h->m1;
+}
+
+const void *cur_set(const hprlp_handle *h) {
+    return h->prec == 1 ? static_cast<const void *>(&h->v32) : static_cast<const void *>(&h->v64);
+}
+
+struct ProfRec {
+    size_t ev0;
+    bool col;
+};
+
+// One iteration (column pass then row pass).  keep: also store w_bar and d = w - w_hat.
+int run_iteration(hprlp_handle *h, bool keep, std::vector<ProfRec> *prof, size_t *ev_next) {
+    IterScalars s;
+    fill_scalars(h, s);
+    const void *vs = cur_set(h);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof) {
+            e0 = pool_event(h, *ev_next);
+            e1 = pool_event(h, *ev_next + 1);
+            if (!e0 || !e1) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
+            prof->push_back({*ev_next, pass == 0});
+            *ev_next += 2;
+            HIPCHK(h, hipEventRecord(e0, h->st));
+        }
+        hipError_t e = pass == 0 ? launch_col_pass(h->prec, keep, h->T, vs, s, h->st)
+                                 : launch_row_pass(h->prec, keep, h->A, vs, s, h->st);
+        if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("pass launch: ") + hipGetErrorString(e));
+        if (prof) HIPCHK(h, hipEventRecord(e1, h->st));
+    }
+    h->t += 1;
+    h->k += 1;
+    return HPRLP_OK;
+}
+
+int run_check(hprlp_handle *h, int slot) {
+    double *outr = h->res + (size_t)(2 * slot) * kNQ;
+    double *outc = outr + kNQ;
+    hipError_t e = launch_check_row(h->prec, h->A, cur_set(h), h->chk, h->v64.bd, h->m1,
+                                    h->partsA, outr, h->st);
+    if (e == hipSuccess)
+        e = launch_check_col(h->prec, h->T, cur_set(h), h->chk, h->v64.cd, h->v64.sc, h->partsT,
+                             outc, h->st);
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("check launch: ") + hipGetErrorString(e));
+    return HPRLP_OK;
+}
+
+double merit_of(const double *q, double sigma, double lambda) {
+    // ||w - w_hat||_M^2 = sigma lambda ||dy||^2 + 2 <dy, A~ dx> + ||dx||^2 / sigma
+    const double v = sigma * lambda * q[3] + 2.0 * q[4] + q[kNQ + 4] / sigma;
+    return std::sqrt(v > 0.0 ? v : 0.0);
+}
+
+int power_method(hprlp_handle *h, int *iters) {
+    const int64_t m = h->m;
+    std::vector<double> v0((size_t)m, 1.0 / std::sqrt((double)m));
+    if (h->mixed)
+        for (int64_t i = 0; i < m; ++i) v0[i] *= h->dr[i];
+    int rc = upload(h, h->vg, v0.data(), (size_t)m);
+    if (rc) return rc;
+    const double one = 1.0;
+    HIPCHK(h, hipMemcpyAsync(h->inv_norm, &one, sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const int maxit = h->opt.power_max_iter;
+    const double tol = h->opt.power_tol;
+    double rq_prev = 0.0, lam = 0.0;
+    int done_it = 0;
+    const int B = 32;
+    for (int k0 = 0; k0 < maxit && !done_it; k0 += B) {
+        const int kb = std::min(B, maxit - k0);
+        for (int kk = 0; kk < kb; ++kk) {
+            hipError_t e = launch_power_iter(h->mixed, h->mixed, h->A, h->T, h->vg, h->w,
+                                             h->v64.sc, h->v64.sr, h->inv_norm, h->partsT,
+                                             h->partsA, h->hist, k0 + kk, h->st);
+            if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("power launch: ") + hipGetErrorString(e));
+        }
+        HIPCHK(h, hipMemcpyAsync(h->pinned, h->hist + k0, kb * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->st));
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        for (int kk = 0; kk < kb; ++kk) {
+            const int it = k0 + kk + 1;
+            const double rq = h->pinned[kk];
+            lam = rq;
+            if (it > 1 && std::fabs(rq - rq_prev) <= tol * rq) {
+                done_it = it;
+                break;
+            }
+            rq_prev = rq;
+            if (it == maxit) done_it = it;
+        }
+    }
+    *iters = done_it;
+    h->lambda = lam;
+    return HPRLP_OK;
+}
+
+int zero_state(hprlp_handle *h) {
+    const long long n = h->n, m = h->m;
+    hipError_t e = hipSuccess;
+    if (h->prec == 1) {
+        for (float *p : {h->v32.xhat, h->v32.x0})
+            if (e == hipSuccess) e = launch_fill_f(p, n, 0.f, h->st);
+        for (float *p : {h->v32.y, h->v32.y0})
+            if (e == hipSuccess) e = launch_fill_f(p, m, 0.f, h->st);
+    } else {
+        for (double *p : {h->v64.xhat, h->v64.x0})
+            if (e == hipSuccess) e = launch_fill(p, n, 0.0, h->st);
+        for (double *p : {h->v64.y, h->v64.y0})
+            if (e == hipSuccess) e = launch_fill(p, m, 0.0, h->st);
+    }
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
+    return HPRLP_OK;
+}
+
+// w^{r+1,0} = w_bar: anchors and current iterate (x is rebuilt from x_hat and x0).
+int restart_copy(hprlp_handle *h) {
+    const long long n = h->n, m = h->m;
+    hipError_t e;
+    if (h->prec == 1) {
+        e = launch_copy_f(h->v32.x0, h->v32.xbar, n, h->st);
+        if (e == hipSuccess) e = launch_copy_f(h->v32.xhat, h->v32.xbar, n, h->st);
+        if (e == hipSuccess) e = launch_copy_f(h->v32.y0, h->v32.ybar, m, h->st);
+        if (e == hipSuccess) e = launch_copy_f(h->v32.y, h->v32.ybar, m, h->st);
+    } else {
+        e = launch_copy_d(h->v64.x0, h->v64.xbar, n, h->st);
+        if (e == hipSuccess) e = launch_copy_d(h->v64.xhat, h->v64.xbar, n, h->st);
+        if (e == hipSuccess) e = launch_copy_d(h->v64.y0, h->v64.ybar, m, h->st);
+        if (e == hipSuccess) e = launch_copy_d(h->v64.y, h->v64.ybar, m, h->st);
+    }
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
+    return HPRLP_OK;
+}
+
+// MIXED: move the FP32 state (and the last w_bar) to FP64 and continue in FP64.
+int promote(hprlp_handle *h) {
+    const long long n = h->n, m = h->m;
+    hipError_t e = hipSuccess;
+    std::pair<double *, const float *> xs[] = {{h->v64.xhat, h->v32.xhat},
+                                                {h->v64.x0, h->v32.x0},
+                                                {h->v64.xbar, h->v32.xbar},
+                                                {h->v64.zint, h->v32.zint},
+                                                {h->v64.dx, h->v32.dx}};
+    std::pair<double *, const float *> ys[] = {{h->v64.y, h->v32.y},
+                                                {h->v64.y0, h->v32.y0},
+                                                {h->v64.ybar, h->v32.ybar},
+                                                {h->v64.dy, h->v32.dy}};
+    for (auto &p : xs)
+        if (e == hipSuccess) e = launch_f2d(p.first, p.second, n, h->st);
+    for (auto &p : ys)
+        if (e == hipSuccess) e = launch_f2d(p.first, p.second, m, h->st);
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
+    h->prec = 2;
+    return HPRLP_OK;
+}
+
+int copy_out(hprlp_handle *h, double *dst, const double *src, long long k) {
+    if (!dst || k == 0) return HPRLP_OK;
+    HIPCHK(h, hipMemcpyAsync(dst, src, (size_t)k * sizeof(double), hipMemcpyDefault, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return HPRLP_OK;
+}
+
+}  // namespace
+
+extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int *status) {
+    if (!h) return fail(nullptr, HPRLP_EINVAL, "null handle");
+    const hprlp_options &o = h->opt;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const double t_start = now_ms();
+    h->trace.clear();
+    h->stats = hprlp_stats_t{};
+    h->prec = h->mixed ? 1 : 0;
+    h->t = h->k = h->r = 0;
+    h->sigma = o.sigma0;
+    int rc;
+    int piters = 0;
+    if (o.lambda_override > 0) {
+        h->lambda = o.lambda_override;
+    } else if ((rc = power_method(h, &piters))) {
+        return rc;
+    }
+    const double t_power = now_ms() - t_start;
+    if (!(h->lambda > 0.0) || !std::isfinite(h->lambda)) {
+        h->stats.status = HPRLP_NUMERICAL;
+        if (status) *status = HPRLP_NUMERICAL;
+        return fail(h, HPRLP_OK, "power method gave lambda <= 0");
+    }
+    if ((rc = zero_state(h))) return rc;
+
+    std::vector<ProfRec> prof;
+    size_t ev_next = 0;
+    std::vector<ProfRec> *pp = o.profile ? &prof : nullptr;
+    double prof_ms[2] = {0, 0};
+    long long prof_n[2] = {0, 0};
+    auto flush_prof = [&]() -> int {
+        for (auto &p : prof) {
+            float ms = 0;
+            HIPCHK(h, hipEventElapsedTime(&ms, h->ev_pool[p.ev0], h->ev_pool[p.ev0 + 1]));
+            prof_ms[p.col ? 0 : 1] += ms;
+            prof_n[p.col ? 0 : 1] += 1;
+        }
+        prof.clear();
+        ev_next = 0;
+        return HPRLP_OK;
+    };
+
+    double merit0 = 0, merit_prev = 0;
+    bool pending_first = false;
+    int st_out = HPRLP_UNSOLVED;
+    long long iters_fp32 = 0;
+    const long long ce = o.check_every;
+    for (;;) {
+        const bool first = h->t == 0;
+        const long long kn = h->k + 1;
+        const bool chk = (kn % ce == 0) || kn >= o.max_iter;
+        if (!first && !chk) {
+            const long long next_check = ((h->k / ce) + 1) * ce;
+            const long long last = std::min(next_check, o.max_iter) - 1;
+            while (h->k + 1 <= last)
+                if ((rc = run_iteration(h, false, pp, &ev_next))) return rc;
+            continue;
+        }
+        if ((rc = run_iteration(h, true, pp, &ev_next))) return rc;
+        if (h->prec == 1) iters_fp32 = h->k;
+        if ((rc = run_check(h, chk ? 1 : 0))) return rc;
+        if (!chk) {
+            pending_first = true;
+            continue;
+        }
+        HIPCHK(h, hipMemcpyAsync(h->pinned, h->res, 4 * kNQ * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->st));
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        if (pp && (rc = flush_prof())) return rc;
+        const double *q0 = h->pinned;            // first iteration of this outer loop
+        const double *q = h->pinned + 2 * kNQ;   // this check
+        const double merit = merit_of(q, h->sigma, h->lambda);
+        if (pending_first) {
+            merit0 = merit_of(q0, h->sigma, h->lambda);
+            merit_prev = merit0;
+            pending_first = false;
+        }
+        if (first) {
+            merit0 = merit;
+            merit_prev = merit;
+        }
+        const double bbc = h->beta_b * h->beta_c;
+        const double rel_p = std::sqrt(q[0]) / (1.0 + h->bnorm);
+        const double rel_d = std::sqrt(q[kNQ + 0]) / (1.0 + h->cnorm);
+        const double pobj = bbc * q[kNQ + 2];
+        const double dobj = bbc * q[2] - q[kNQ + 3];
+        const double rel_gap = std::fabs(dobj - pobj) / (1.0 + std::fabs(dobj) + std::fabs(pobj));
+        const double kkt = std::max(rel_gap, std::max(rel_p, rel_d));
+        std::array<double, TR_NCOL> row{};
+        row[TR_K] = (double)h->k; row[TR_T] = (double)h->t; row[TR_R] = (double)h->r;
+        row[TR_SIGMA] = h->sigma; row[TR_MERIT] = merit; row[TR_MERIT0] = merit0;
+        row[TR_MERIT_PREV] = merit_prev; row[TR_REL_P] = rel_p; row[TR_REL_D] = rel_d;
+        row[TR_REL_GAP] = rel_gap; row[TR_POBJ] = pobj; row[TR_DOBJ] = dobj;
+        row[TR_SIGMA_NEW] = h->sigma;
+        h->stats.rel_p = rel_p; h->stats.rel_d = rel_d; h->stats.rel_gap = rel_gap;
+        h->stats.pobj = pobj; h->stats.dobj = dobj;
+        if (o.verbose)
+            std::fprintf(stderr, "hprlp k=%lld r=%lld t=%lld sigma=%.3e p=%.2e d=%.2e g=%.2e merit=%.3e/%.3e\n",
+                         h->k, h->r, h->t, h->sigma, rel_p, rel_d, rel_gap, merit, merit0);
+        const double elapsed_s = (now_ms() - t_start) / 1000.0;
+        if (!(kkt == kkt)) st_out = HPRLP_NUMERICAL;
+        else if (kkt <= o.tol) st_out = HPRLP_OPTIMAL;
+        else if (h->k >= o.max_iter) st_out = HPRLP_ITER_LIMIT;
+        else if (o.time_limit > 0 && elapsed_s >= o.time_limit) st_out = HPRLP_TIME_LIMIT;
+        if (st_out != HPRLP_UNSOLVED) {
+            h->trace.push_back(row);
+            break;
+        }
+        // ---- restart criteria (Section 3.1), with the reading documented in DESIGN notes
+        bool restart = false;
+        if (o.use_restart) {
+            if (merit <= o.alpha1 * merit0) restart = true;
+            if (merit <= o.alpha2 * merit0 && merit > merit_prev) restart = true;
+            if ((double)h->t >= o.alpha3 * (double)h->k) restart = true;
+        }
+        if (restart) {
+            double sig_new = h->sigma;
+            if (o.sigma_update) {  // Algorithm 3 with eq. sigma_T1!=0
+                const double Dx = std::sqrt(q[kNQ + 5]);
+                const double Dy = std::sqrt(h->lambda) * std::sqrt(q[5]);
+                const double err_p = std::sqrt(q[1]) / (1.0 + h->bsnorm);
+                const double err_d = std::sqrt(q[kNQ + 1]) / (1.0 + h->csnorm);
+                const bool ok = Dx > 1e-16 && Dx < 1e12 && Dy > 1e-16 && Dy < 1e12 &&
+                                err_p > 0.0 && err_d / err_p > 1e-8 && err_d / err_p < 1e8;
+                sig_new = ok ? Dx / Dy : 1.0;
+                row[TR_DX] = Dx; row[TR_DY] = Dy; row[TR_ERR_P] = err_p; row[TR_ERR_D] = err_d;
+            }
+            row[TR_RESTART] = 1.0;
+            row[TR_SIGMA_NEW] = sig_new;
+            h->sigma = sig_new;
+            if ((rc = restart_copy(h))) return rc;
+            h->t = 0;
+            h->r += 1;
+        } else {
+            merit_prev = merit;
+        }
+        h->trace.push_back(row);
+        if (h->prec == 1 && kkt <= o.tol_switch)
+            if ((rc = promote(h))) return rc;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    if (pp && (rc = flush_prof())) return rc;
+    // ---- outputs: w_bar of the last check, original space
+    const bool f32 = h->prec == 1;
+    const void *xb = f32 ? (const void *)h->v32.xbar : (const void *)h->v64.xbar;
+    const void *yb = f32 ? (const void *)h->v32.ybar : (const void *)h->v64.ybar;
+    const void *zb = f32 ? (const void *)h->v32.zint : (const void *)h->v64.zint;
+    double *ox = h->outv, *oy = h->outv + h->n, *oz = h->outv + h->n + h->m;
+    hipError_t e = launch_scale_out(ox, xb, f32, h->ux, 0.0, h->n, h->st);
+    if (e == hipSuccess) e = launch_scale_out(oy, yb, f32, h->uy, 0.0, h->m, h->st);
+    if (e == hipSuccess) e = launch_scale_out(oz, zb, f32, h->chk.co, 0.0, h->n, h->st);
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const double t_end = now_ms();
+    if ((rc = copy_out(h, x, ox, h->n)) || (rc = copy_out(h, y, oy, h->m)) ||
+        (rc = copy_out(h, z, oz, h->n)))
+        return rc;
+    h->solved = true;
+    hprlp_stats_t &s = h->stats;
+    s.iters = h->k;
+    s.restarts = h->r;
+    s.iters_fp32 = h->mixed ? iters_fp32 : 0;
+    s.status = st_out;
+    s.power_iters = piters;
+    s.sigma = h->sigma;
+    s.lambda = h->lambda;
+    s.beta_b = h->beta_b;
+    s.beta_c = h->beta_c;
+    s.t_power_ms = t_power;
+    s.t_solve_ms = t_end - t_start;
+    const double sv = h->mixed ? 4.0 : 8.0, svec = (h->prec == 1) ? 4.0 : 8.0;
+    s.bytes_per_iter = 2.0 * h->nnz * (sv + 4.0) + 4.0 * (h->m + h->n + 2) + 7.0 * h->n * svec +
+                       5.0 * h->m * svec;
+    s.col_pass_ms = prof_ms[0];
+    s.row_pass_ms = prof_ms[1];
+    s.col_pass_launches = prof_n[0];
+    s.row_pass_launches = prof_n[1];
+    s.n_checks = (long long)h->trace.size();
+    if (status) *status = st_out;
+    return HPRLP_OK;
+}
+
+extern "C" int hprlp_stats(const hprlp_handle *h, hprlp_stats_t *out) {
+    if (!h || !out) return fail(const_cast<hprlp_handle *>(h), HPRLP_EINVAL, "null argument");
+    *out = h->stats;
+    return HPRLP_OK;
+}
+
+extern "C" int hprlp_get_iterate(const hprlp_handle *hc, int which, double *out) {
+    hprlp_handle *h = const_cast<hprlp_handle *>(hc);
+    if (!h || !out) return fail(h, HPRLP_EINVAL, "null argument");
+    if (which == HPRLP_DROW || which == HPRLP_DCOL) {
+        const std::vector<double> &d = which == HPRLP_DROW ? h->dr : h->dc;
+        HIPCHK(h, hipMemcpy(out, d.data(), d.size() * sizeof(double), hipMemcpyDefault));
+        return HPRLP_OK;
+    }
+    if (!h->solved) return fail(h, HPRLP_ESTATE, "no solve has run yet");
+    const bool f32 = h->prec == 1;
+    double *tmp = h->outv;
+    hipError_t e = hipSuccess;
+    long long len = 0;
+    switch (which) {
+    case HPRLP_XBAR:
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.xbar : h->v64.xbar, f32, h->ux, 0, h->n, h->st);
+        len = h->n;
+        break;
+    case HPRLP_YBAR:
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.ybar : h->v64.ybar, f32, h->uy, 0, h->m, h->st);
+        len = h->m;
+        break;
+    case HPRLP_ZBAR:
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.zint : h->v64.zint, f32, h->chk.co, 0, h->n, h->st);
+        len = h->n;
+        break;
+    case HPRLP_XCUR: {
+        IterScalars s;
+        fill_scalars(h, s);
+        e = launch_xcur_out(tmp, f32 ? (const void *)h->v32.x0 : h->v64.x0,
+                            f32 ? (const void *)h->v32.xhat : h->v64.xhat, f32, s.hx0, s.hx1,
+                            h->ux, 0, h->n, h->st);
+        len = h->n;
+        break;
+    }
+    case HPRLP_YCUR:
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.y : h->v64.y, f32, h->uy, 0, h->m, h->st);
+        len = h->m;
+        break;
+    default:
+        return fail(h, HPRLP_EINVAL, "unknown iterate");
+    }
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
+    return copy_out(h, out, tmp, len);
+}
+
+extern "C" int hprlp_get_trace(const hprlp_handle *hc, double *out, long long cap,
+                               long long *n_rows) {
+    hprlp_handle *h = const_cast<hprlp_handle *>(hc);
+    if (!h || !n_rows) return fail(h, HPRLP_EINVAL, "null argument");
+    *n_rows = (long long)h->trace.size();
+    if (out)
+        for (long long i = 0; i < std::min<long long>(cap, *n_rows); ++i)
+            std::memcpy(out + i * TR_NCOL, h->trace[i].data(), TR_NCOL * sizeof(double));
+    return HPRLP_OK;
+}
+
+extern "C" int hprlp_time_passes(hprlp_handle *h, int reps, double *col_ms, double *row_ms) {
+    if (!h || reps < 1) return fail(h, HPRLP_EINVAL, "bad argument");
+    if (!h->solved) return fail(h, HPRLP_ESTATE, "call after a solve");
+    IterScalars s;
+    fill_scalars(h, s);
+    const void *vs = cur_set(h);
+    hipEvent_t e[4];
+    for (int i = 0; i < 4; ++i) {
+        e[i] = pool_event(h, i);
+        if (!e[i]) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
+    }
+    HIPCHK(h, hipEventRecord(e[0], h->st));
+    for (int i = 0; i < reps; ++i) {
+        hipError_t r = launch_col_pass(h->prec, false, h->T, vs, s, h->st);
+        if (r != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(r));
+    }
+    HIPCHK(h, hipEventRecord(e[1], h->st));
+    HIPCHK(h, hipEventRecord(e[2], h->st));
+    for (int i = 0; i < reps; ++i) {
+        hipError_t r = launch_row_pass(h->prec, false, h->A, vs, s, h->st);
+        if (r != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(r));
+    }
+    HIPCHK(h, hipEventRecord(e[3], h->st));
+    HIPCHK(h, hipEventSynchronize(e[3]));
+    float a = 0, b = 0;
+    HIPCHK(h, hipEventElapsedTime(&a, e[0], e[1]));
+    HIPCHK(h, hipEventElapsedTime(&b, e[2], e[3]));
+    if (col_ms) *col_ms = a / reps;
+    if (row_ms) *row_ms = b / reps;
+    return HPRLP_OK;
+}
+
+extern "C" const char *hprlp_last_error(const hprlp_handle *h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" void hprlp_destroy(hprlp_handle *h) {
+    if (!h) return;
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    delete h;
+}

@@ -1,0 +1,118 @@
+// Internal declarations shared by the host runtime (api.cpp, setup.cpp) and the HIP kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hprlp.h"
+
+namespace hprlp {
+
+constexpr int kWG = 256;          // threads per workgroup of the SpMV passes (4 wavefronts)
+constexpr int kNQ = 6;            // check quantities per pass (row pass and column pass)
+
+// Work-item kinds of a pass schedule.  One workgroup processes one item.
+enum ItemKind : int { IT_TILE = 0, IT_ROW = 1, IT_CHUNK = 2 };
+
+// Schedule of one CSR matrix (host side, then uploaded).
+//   TILE : {r0, r1, inst, IT_TILE}   rows [r0, r1), all short, nnz <= tile_nnz
+//   ROW  : {r, inst, 0, IT_ROW}      one long row, whole workgroup
+//   CHUNK: {p0, p1, slot, IT_CHUNK}  a piece of a split row; partial sum -> split_part[slot]
+// splits: {row, slot0, nslots, inst} finished (fixed-order sum + epilogue) by a second kernel.
+struct Schedule {
+    std::vector<int4> items;
+    std::vector<int4> splits;
+    int n_chunk_slots = 0;
+    int tile_nnz = 0, tile_rows = 0;
+    long long n_tiles = 0, n_rowitems = 0, n_chunks = 0;
+};
+
+struct ScheduleParams {
+    int tile_nnz, tile_rows, short_max, split_len, chunk_nnz;
+};
+
+void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &sp,
+                    const int32_t *inst_of_row /* nullable */, Schedule &out);
+
+// A CSR matrix resident in the workspace.
+struct DevMat {
+    int rows = 0;
+    int *rp = nullptr;          // int32[rows+1]
+    int *ci = nullptr;          // int32[nnz]
+    void *va = nullptr;         // double[nnz] (FP64 mode: scaled A~) or float[nnz] (MIXED: A)
+    int4 *items = nullptr;
+    int n_items = 0;
+    int4 *splits = nullptr;
+    int n_split = 0;
+    void *split_part = nullptr; // partial sums of split rows (max 16 B per slot)
+    int tile_nnz = 0, tile_rows = 0;
+    Schedule host;              // kept for stats / re-upload
+};
+
+// Iterate state and per-iteration data vectors in one precision V.
+// Internal coordinates: FP64 mode works on the scaled problem (x~, y~); MIXED works on
+// x' = D_c x~ and y' = D_r y~ (= original / beta), with the original FP32-exact A and the
+// diagonal scaling folded into the passes (sc = dc^2, sr = dr^2).
+template <class V> struct VecSet {
+    V *xhat = nullptr, *x0 = nullptr, *cd = nullptr, *ld = nullptr, *ud = nullptr,
+      *sc = nullptr;
+    V *xbar = nullptr, *zint = nullptr, *dx = nullptr;
+    V *y = nullptr, *y0 = nullptr, *bd = nullptr, *sr = nullptr;
+    V *ybar = nullptr, *dy = nullptr;
+};
+
+// Scalars of one pass launch.
+struct IterScalars {
+    double sigma;       // sigma_r
+    double lam_sigma;   // lambda * sigma_r
+    double hx0, hx1;    // x^{r,t} = hx0 * x0 + hx1 * x_hat     (Halpern weights at t)
+    double hy0, hy1;    // y^{r,t+1} = hy0 * y0 + hy1 * y_hat   (Halpern weights at t)
+    long long m1;       // first inequality row (single LP)
+};
+
+// Check-pass multipliers (always FP64).
+struct CheckData {
+    double *ro = nullptr, *rs = nullptr, *ys = nullptr;  // per row
+    double *co = nullptr, *cs = nullptr, *xs = nullptr;  // per column
+    double *lo = nullptr, *uo = nullptr;                 // original bounds
+};
+
+// ---------------------------------------------------------------- kernel launchers
+// prec: 0 = FP64 (double A, double vectors, no fold); 1 = MIXED FP32 phase (float A, float
+// vectors, fold); 2 = MIXED FP64 phase (float A, double vectors, fold).
+hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vecset,
+                           const IterScalars &s, hipStream_t st);
+hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vecset,
+                           const IterScalars &s, hipStream_t st);
+// check passes: write kNQ partial sums per slot into parts, then reduce into out[kNQ]
+// bd64 / cd64 / sc64: FP64 right-hand side, cost and folded column scaling (dc^2, MIXED only)
+hipError_t launch_check_row(int prec, const DevMat &A, const void *vecset, const CheckData &cd,
+                            const double *bd64, long long m1, double *parts, double *out,
+                            hipStream_t st);
+hipError_t launch_check_col(int prec, const DevMat &T, const void *vecset, const CheckData &cd,
+                            const double *cd64, const double *sc64, double *parts, double *out,
+                            hipStream_t st);
+// power method iteration k (0-based): hist[k] = Rayleigh quotient, inv_norm updated
+hipError_t launch_power_iter(bool mat_f32, bool fold, const DevMat &A, const DevMat &T,
+                             double *vg, double *w, const double *sc, const double *sr,
+                             double *inv_norm, double *parts_c, double *parts_r, double *hist,
+                             int k, hipStream_t st);
+// vector utilities
+hipError_t launch_fill(double *p, long long n, double v, hipStream_t st);
+hipError_t launch_fill_f(float *p, long long n, float v, hipStream_t st);
+hipError_t launch_copy_d(double *dst, const double *src, long long n, hipStream_t st);
+hipError_t launch_copy_f(float *dst, const float *src, long long n, hipStream_t st);
+hipError_t launch_f2d(double *dst, const float *src, long long n, hipStream_t st);
+// out = mul[i] * v[i] (mul == nullptr -> scalar smul); v in float or double
+hipError_t launch_scale_out(double *out, const void *v, bool v_f32, const double *mul,
+                            double smul, long long n, hipStream_t st);
+// x^{r,t} = hx0 * x0 + hx1 * xhat, scaled by mul/smul
+hipError_t launch_xcur_out(double *out, const void *x0, const void *xhat, bool v_f32,
+                           double hx0, double hx1, const double *mul, double smul, long long n,
+                           hipStream_t st);
+
+}  // namespace hprlp

@@ -1,0 +1,649 @@
+// HIP kernels of the HPR-LP iteration for gfx950 (CDNA4).
+//
+// The two sparse products of one iteration (Section 3.3 of the paper: eqs. update-z,
+// update-x and update-y-2) are each ONE binned CSR SpMV launch whose epilogue applies the
+// whole vector update of that half-step: projection onto the box C or the cone D,
+// reflection w_hat = 2 w_bar - w, and the Halpern averaging of Algorithm 2.  The stored
+// transpose turns A^T y into a row-wise product, so no pass needs atomics and every sum is
+// taken in a fixed order (bit-reproducible runs).
+//
+// Work items (one 256-thread workgroup each, see Schedule):
+//   TILE   a run of consecutive short rows holding <= tile_nnz nonzeros.  Phase 1 streams the
+//          tile's nonzeros with fully coalesced loads and stages the products in LDS;
+//          phase 2 sums each row from LDS with a group of G lanes (G = power of two sized to
+//          the tile's rows, reduced by cross-lane shuffles); phase 3 runs the epilogue with
+//          one thread per row, so vector loads/stores of the epilogue are coalesced too.
+//   ROW    one long row summed by the whole workgroup (wavefront shuffles + LDS).
+//   CHUNK  a slice of a very long row; its partial sum goes to a slot and a second small
+//          kernel adds the slots of each split row in index order and runs the epilogue.
+// Check passes (every check_every iterations) reuse the same kernel with epilogues that
+// produce per-workgroup partial sums of the termination / restart / sigma quantities,
+// reduced by a single-workgroup kernel in a fixed order.
+#include "hprlp_internal.h"
+
+namespace hprlp {
+namespace {
+
+struct D2 {
+    double a, b;
+};
+__device__ __forceinline__ D2 operator+(D2 x, D2 y) { return D2{x.a + y.a, x.b + y.b}; }
+
+template <class S> __device__ __forceinline__ S szero();
+template <> __device__ __forceinline__ float szero<float>() { return 0.f; }
+template <> __device__ __forceinline__ double szero<double>() { return 0.0; }
+template <> __device__ __forceinline__ D2 szero<D2>() { return D2{0.0, 0.0}; }
+
+__device__ __forceinline__ float xshfl(float v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ double xshfl(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ D2 xshfl(D2 v, int m) {
+    return D2{__shfl_xor(v.a, m, 64), __shfl_xor(v.b, m, 64)};
+}
+
+template <class S> __device__ __forceinline__ S wave_sum(S v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = v + xshfl(v, off);
+    return v;
+}
+
+// Sum over the 256 threads of the workgroup; the result is valid in thread 0.
+template <class S> __device__ __forceinline__ S block_sum(S v, S *red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    S t = szero<S>();
+    if (threadIdx.x == 0) t = ((red[0] + red[1]) + red[2]) + red[3];
+    return t;
+}
+
+template <class V> __device__ __forceinline__ V vmin(V a, V b) { return a < b ? a : b; }
+template <class V> __device__ __forceinline__ V vmax(V a, V b) { return a > b ? a : b; }
+// Box projection with +-inf bounds (fmin/fmax semantics: a NaN bound is never produced).
+template <class V> __device__ __forceinline__ V clampv(V v, V lo, V hi) {
+    return vmin(vmax(v, lo), hi);
+}
+
+template <class M, class V> struct AccT { using type = double; };
+template <> struct AccT<float, float> { using type = float; };
+
+// ------------------------------------------------------------------------- the SpMV kernel
+
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
+                                              const int *__restrict__ rp, Op op,
+                                              typename Op::Sum *__restrict__ split_part,
+                                              double *__restrict__ parts) {
+    using S = typename Op::Sum;
+    constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ S red[4];
+    __shared__ double redq[4];
+    const int4 it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    double q[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) q[j] = 0.0;
+
+    if (it.w == IT_TILE) {
+        S *prod = reinterpret_cast<S *>(smem);
+        S *rsum = prod + op.tile_nnz;
+        const int r0 = it.x, r1 = it.y, inst = it.z;
+        const int P0 = rp[r0];
+        const int cnt = rp[r1] - P0;
+#pragma unroll 4
+        for (int k = tid; k < cnt; k += kWG) prod[k] = op.prod(P0 + k);
+        __syncthreads();
+        const int nrows = r1 - r0;
+        int G = 1;
+        while (G < 64 && 2 * G * nrows <= kWG) G <<= 1;
+        const int lg = tid & (G - 1);
+        const int ng = kWG / G;
+        for (int rr = tid / G; rr < nrows; rr += ng) {
+            const int b = rp[r0 + rr] - P0, e = rp[r0 + rr + 1] - P0;
+            S s = szero<S>();
+            for (int k = b + lg; k < e; k += G) s = s + prod[k];
+            for (int off = G >> 1; off > 0; off >>= 1) s = s + xshfl(s, off);
+            if (lg == 0) rsum[rr] = s;
+        }
+        __syncthreads();
+        for (int rr = tid; rr < nrows; rr += kWG) op.epilogue(r0 + rr, rsum[rr], inst, q);
+    } else if (it.w == IT_ROW) {
+        const int r = it.x, inst = it.y;
+        const int b = rp[r], e = rp[r + 1];
+        S s = szero<S>();
+#pragma unroll 4
+        for (int k = b + tid; k < e; k += kWG) s = s + op.prod(k);
+        s = block_sum(s, red);
+        if (tid == 0) op.epilogue(r, s, inst, q);
+    } else {
+        S s = szero<S>();
+#pragma unroll 4
+        for (int k = it.x + tid; k < it.y; k += kWG) s = s + op.prod(k);
+        s = block_sum(s, red);
+        if (tid == 0) split_part[it.z] = s;
+    }
+    if constexpr (Op::NQ > 0) {
+#pragma unroll
+        for (int j = 0; j < Op::NQ; ++j) {
+            const double t = block_sum(q[j], redq);
+            if (tid == 0) parts[(size_t)blockIdx.x * Op::NQ + j] = t;
+        }
+    }
+}
+
+// Finish split rows: one wavefront per split row sums its slots in index order.
+template <class Op>
+__global__ __launch_bounds__(64) void k_split(const int4 *__restrict__ splits,
+                                              const typename Op::Sum *__restrict__ part, Op op,
+                                              double *__restrict__ parts, int slot_base) {
+    using S = typename Op::Sum;
+    constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
+    const int4 sp = splits[blockIdx.x];
+    S s = szero<S>();
+    for (int k = threadIdx.x; k < sp.z; k += 64) s = s + part[sp.y + k];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+        double q[NQ];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) q[j] = 0.0;
+        op.epilogue(sp.x, s, sp.w, q);
+        if constexpr (Op::NQ > 0) {
+#pragma unroll
+            for (int j = 0; j < Op::NQ; ++j)
+                parts[(size_t)(slot_base + blockIdx.x) * Op::NQ + j] = q[j];
+        }
+    }
+}
+
+// Fixed-order reduction of per-workgroup partials: out[j] = sum_k parts[k*nq + j].
+__global__ __launch_bounds__(kWG) void k_reduce(const double *__restrict__ parts, int nslots,
+                                                int nq, double *__restrict__ out) {
+    __shared__ double red[4];
+    for (int j = 0; j < nq; ++j) {
+        double s = 0.0;
+        for (int k = threadIdx.x; k < nslots; k += kWG) s += parts[(size_t)k * nq + j];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) out[j] = s;
+    }
+}
+
+// ------------------------------------------------------------------------- epilogues
+
+// x-step over A^T (eqs. update-z/x): rows of A^T are the columns j of A.
+//   x      = hx0 x0 + hx1 x_hat                 (x^{r,t}, rebuilt from the Halpern anchor)
+//   v      = x + sigma * s_j (g - c)             (s_j = dc_j^2 when the scaling is folded)
+//   x_bar  = Pi_C(v);   x_hat <- 2 x_bar - x     (gathered by the y-step)
+//   keep:  x_bar, z_int = (x_bar - v)/sigma (eq. update-z), dx = x - x_hat
+template <class M, class V, bool FOLD, bool KEEP> struct ColOp {
+    using Sum = typename AccT<M, V>::type;
+    static constexpr int NQ = 0;
+    int tile_nnz;
+    const int *__restrict__ ci;
+    const M *__restrict__ va;
+    const V *__restrict__ yg;
+    V *__restrict__ xhat;
+    const V *__restrict__ x0;
+    const V *__restrict__ cd;
+    const V *__restrict__ ld;
+    const V *__restrict__ ud;
+    const V *__restrict__ sc;
+    V *__restrict__ xbar;
+    V *__restrict__ zint;
+    V *__restrict__ dx;
+    V sigma, hx0, hx1;
+    __device__ __forceinline__ Sum prod(int p) const { return (Sum)va[p] * (Sum)yg[ci[p]]; }
+    __device__ __forceinline__ void epilogue(int j, Sum g, int, double *) const {
+        const V x = hx0 * x0[j] + hx1 * xhat[j];
+        V gs = (V)g - cd[j];
+        if (FOLD) gs = sc[j] * gs;
+        const V v = x + sigma * gs;
+        const V xb = clampv(v, ld[j], ud[j]);
+        const V xr = (V)2 * xb - x;
+        xhat[j] = xr;
+        if (KEEP) {
+            xbar[j] = xb;
+            zint[j] = (xb - v) / sigma;
+            dx[j] = x - xr;
+        }
+    }
+};
+
+// y-step over A (eq. update-y-2 with T1 = lambda I - A A^T):
+//   y_bar = y + r_i (b - A x_hat)/(lambda sigma)  (r_i = dr_i^2 when folded);
+//   y_bar = max(y_bar, 0) on inequality rows;   y <- hy0 y0 + hy1 (2 y_bar - y)
+//   keep:  y_bar, dy = y - y_hat
+template <class M, class V, bool FOLD, bool KEEP> struct RowOp {
+    using Sum = typename AccT<M, V>::type;
+    static constexpr int NQ = 0;
+    int tile_nnz;
+    const int *__restrict__ ci;
+    const M *__restrict__ va;
+    const V *__restrict__ xg;
+    V *__restrict__ y;
+    const V *__restrict__ y0;
+    const V *__restrict__ bd;
+    const V *__restrict__ sr;
+    V *__restrict__ ybar;
+    V *__restrict__ dy;
+    V lam_sigma, hy0, hy1;
+    long long m1;
+    __device__ __forceinline__ Sum prod(int p) const { return (Sum)va[p] * (Sum)xg[ci[p]]; }
+    __device__ __forceinline__ void epilogue(int i, Sum s, int, double *) const {
+        const V yv = y[i];
+        V r = bd[i] - (V)s;
+        if (FOLD) r = sr[i] * r;
+        V yb = yv + r / lam_sigma;
+        if (i >= m1) yb = vmax(yb, (V)0);
+        const V yr = (V)2 * yb - yv;
+        y[i] = hy0 * y0[i] + hy1 * yr;
+        if (KEEP) {
+            ybar[i] = yb;
+            dy[i] = yv - yr;
+        }
+    }
+};
+
+// Check, row side (FP64): p = A x_bar and q = A dx from one pass over A.
+//   q0 = ||Pi_D(b - A x)||^2 (original data)   q1 = same on the scaled data (sigma update)
+//   q2 = <b, y_bar> / (beta_b beta_c)          q3 = ||dy||^2 (scaled)
+//   q4 = <dy, A~ dx>                           q5 = ||y_bar - y0||^2 (scaled)
+template <class M, class V> struct CheckRowOp {
+    using Sum = D2;
+    static constexpr int NQ = kNQ;
+    int tile_nnz;
+    const int *__restrict__ ci;
+    const M *__restrict__ va;
+    const V *__restrict__ xbar;
+    const V *__restrict__ dxv;
+    const V *__restrict__ ybar;
+    const V *__restrict__ dyv;
+    const V *__restrict__ y0;
+    const double *__restrict__ bd;
+    const double *__restrict__ ro;
+    const double *__restrict__ rs;
+    const double *__restrict__ ys;
+    long long m1;
+    __device__ __forceinline__ Sum prod(int p) const {
+        const double a = (double)va[p];
+        const int j = ci[p];
+        return D2{a * (double)xbar[j], a * (double)dxv[j]};
+    }
+    __device__ __forceinline__ void epilogue(int i, Sum s, int, double *q) const {
+        const double e = bd[i] - s.a;
+        double eo = ro[i] * e, es = rs[i] * e;
+        if (i >= m1) {
+            eo = eo > 0.0 ? eo : 0.0;
+            es = es > 0.0 ? es : 0.0;
+        }
+        q[0] += eo * eo;
+        q[1] += es * es;
+        const double yb = (double)ybar[i];
+        q[2] += bd[i] * yb;
+        const double dyi = (double)dyv[i];
+        const double d = ys[i] * dyi;
+        q[3] += d * d;
+        q[4] += dyi * s.b;
+        const double e2 = ys[i] * (yb - (double)y0[i]);
+        q[5] += e2 * e2;
+    }
+};
+
+// Check, column side (FP64): g = A^T y_bar.
+//   q0 = ||c - A^T y - z||^2 (original)   q1 = same on the scaled data
+//   q2 = <c, x_bar> / (beta_b beta_c)     q3 = delta*_C(-z) (original, 0*inf := 0)
+//   q4 = ||dx||^2 (scaled)                q5 = ||x_bar - x0||^2 (scaled)
+template <class M, class V, bool FOLD> struct CheckColOp {
+    using Sum = double;
+    static constexpr int NQ = kNQ;
+    int tile_nnz;
+    const int *__restrict__ ci;
+    const M *__restrict__ va;
+    const V *__restrict__ ybar;
+    const V *__restrict__ xbar;
+    const V *__restrict__ zint;
+    const V *__restrict__ dxv;
+    const V *__restrict__ x0;
+    const double *__restrict__ cd;
+    const double *__restrict__ sc;
+    const double *__restrict__ co;
+    const double *__restrict__ cs;
+    const double *__restrict__ xs;
+    const double *__restrict__ lo;
+    const double *__restrict__ uo;
+    __device__ __forceinline__ Sum prod(int p) const {
+        return (double)va[p] * (double)ybar[ci[p]];
+    }
+    __device__ __forceinline__ void epilogue(int j, Sum g, int, double *q) const {
+        const double xb = (double)xbar[j];
+        const double zi = (double)zint[j];
+        double e = cd[j] - g;
+        if (FOLD) e = sc[j] * e;
+        e = e - zi;
+        const double eo = co[j] * e, es = cs[j] * e;
+        q[0] += eo * eo;
+        q[1] += es * es;
+        q[2] += cd[j] * xb;
+        const double zo = co[j] * zi;
+        double sup = 0.0;
+        if (zo < 0.0) sup = -zo * uo[j];
+        else if (zo > 0.0) sup = -zo * lo[j];
+        q[3] += sup;
+        const double d = xs[j] * (double)dxv[j];
+        q[4] += d * d;
+        const double e2 = xs[j] * (xb - (double)x0[j]);
+        q[5] += e2 * e2;
+    }
+};
+
+// Power method on A~ A~^T (Section 4.1), FP64.  With the scaling folded, the vectors that
+// are gathered carry the diagonal factors: vg = D_r v, w = D_c A~^T v.
+template <class M, bool FOLD> struct PowColOp {
+    using Sum = double;
+    static constexpr int NQ = 1;
+    int tile_nnz;
+    const int *__restrict__ ci;
+    const M *__restrict__ va;
+    const double *__restrict__ vg;
+    const double *__restrict__ inv_norm;
+    double *__restrict__ w;
+    const double *__restrict__ sc;
+    __device__ __forceinline__ Sum prod(int p) const { return (double)va[p] * vg[ci[p]]; }
+    __device__ __forceinline__ void epilogue(int j, Sum g, int, double *q) const {
+        const double gn = g * (*inv_norm);
+        const double t = FOLD ? sc[j] * gn : gn;
+        w[j] = t;
+        q[0] += t * gn;  // ||A~^T v||^2
+    }
+};
+
+template <class M, bool FOLD> struct PowRowOp {
+    using Sum = double;
+    static constexpr int NQ = 1;
+    int tile_nnz;
+    const int *__restrict__ ci;
+    const M *__restrict__ va;
+    const double *__restrict__ w;
+    double *__restrict__ vg;
+    const double *__restrict__ sr;
+    __device__ __forceinline__ Sum prod(int p) const { return (double)va[p] * w[ci[p]]; }
+    __device__ __forceinline__ void epilogue(int i, Sum s, int, double *q) const {
+        const double t = FOLD ? sr[i] * s : s;
+        vg[i] = t;
+        q[0] += t * s;  // ||A~ A~^T v||^2
+    }
+};
+
+__global__ __launch_bounds__(kWG) void k_power_reduce(const double *__restrict__ pc, int nc,
+                                                      const double *__restrict__ pr, int nr,
+                                                      double *__restrict__ hist,
+                                                      double *__restrict__ inv_norm) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nc; k += kWG) s += pc[k];
+    s = block_sum(s, red);
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nr; k += kWG) t += pr[k];
+    t = block_sum(t, red);
+    if (threadIdx.x == 0) {
+        *hist = s;
+        *inv_norm = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------- launch helpers
+
+template <class Op>
+hipError_t run_pass(const DevMat &M, Op op, double *parts, hipStream_t st) {
+    using S = typename Op::Sum;
+    op.tile_nnz = M.tile_nnz;
+    const size_t lds = (size_t)(M.tile_nnz + M.tile_rows) * sizeof(S);
+    if (M.n_items > 0)
+        hipLaunchKernelGGL(k_pass<Op>, dim3(M.n_items), dim3(kWG), lds, st, M.items, M.rp, op,
+                           reinterpret_cast<S *>(M.split_part), parts);
+    if (M.n_split > 0)
+        hipLaunchKernelGGL(k_split<Op>, dim3(M.n_split), dim3(64), 0, st, M.splits,
+                           reinterpret_cast<const S *>(M.split_part), op, parts, M.n_items);
+    return hipGetLastError();
+}
+
+template <class M, class V, bool FOLD, bool KEEP>
+hipError_t col_pass(const DevMat &T, const VecSet<V> &v, const IterScalars &s, hipStream_t st) {
+    ColOp<M, V, FOLD, KEEP> op;
+    op.ci = T.ci;
+    op.va = reinterpret_cast<const M *>(T.va);
+    op.yg = v.y;
+    op.xhat = v.xhat; op.x0 = v.x0; op.cd = v.cd; op.ld = v.ld; op.ud = v.ud; op.sc = v.sc;
+    op.xbar = v.xbar; op.zint = v.zint; op.dx = v.dx;
+    op.sigma = (V)s.sigma; op.hx0 = (V)s.hx0; op.hx1 = (V)s.hx1;
+    return run_pass(T, op, nullptr, st);
+}
+
+template <class M, class V, bool FOLD, bool KEEP>
+hipError_t row_pass(const DevMat &A, const VecSet<V> &v, const IterScalars &s, hipStream_t st) {
+    RowOp<M, V, FOLD, KEEP> op;
+    op.ci = A.ci;
+    op.va = reinterpret_cast<const M *>(A.va);
+    op.xg = v.xhat;
+    op.y = v.y; op.y0 = v.y0; op.bd = v.bd; op.sr = v.sr; op.ybar = v.ybar; op.dy = v.dy;
+    op.lam_sigma = (V)s.lam_sigma; op.hy0 = (V)s.hy0; op.hy1 = (V)s.hy1;
+    op.m1 = s.m1;
+    return run_pass(A, op, nullptr, st);
+}
+
+template <class M, class V>
+hipError_t check_row(const DevMat &A, const VecSet<V> &v, const CheckData &cd, const double *bd,
+                     long long m1, double *parts, double *out, hipStream_t st) {
+    CheckRowOp<M, V> op;
+    op.ci = A.ci;
+    op.va = reinterpret_cast<const M *>(A.va);
+    op.xbar = v.xbar; op.dxv = v.dx; op.ybar = v.ybar; op.dyv = v.dy; op.y0 = v.y0;
+    op.bd = bd; op.ro = cd.ro; op.rs = cd.rs; op.ys = cd.ys; op.m1 = m1;
+    hipError_t e = run_pass(A, op, parts, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, parts, A.n_items + A.n_split, kNQ,
+                       out);
+    return hipGetLastError();
+}
+
+template <class M, class V, bool FOLD>
+hipError_t check_col(const DevMat &T, const VecSet<V> &v, const CheckData &cd, const double *cdv,
+                     const double *sc, double *parts, double *out, hipStream_t st) {
+    CheckColOp<M, V, FOLD> op;
+    op.ci = T.ci;
+    op.va = reinterpret_cast<const M *>(T.va);
+    op.ybar = v.ybar; op.xbar = v.xbar; op.zint = v.zint; op.dxv = v.dx; op.x0 = v.x0;
+    op.cd = cdv; op.sc = sc; op.co = cd.co; op.cs = cd.cs; op.xs = cd.xs;
+    op.lo = cd.lo; op.uo = cd.uo;
+    hipError_t e = run_pass(T, op, parts, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, parts, T.n_items + T.n_split, kNQ,
+                       out);
+    return hipGetLastError();
+}
+
+template <class M, bool FOLD>
+hipError_t power_iter(const DevMat &A, const DevMat &T, double *vg, double *w, const double *sc,
+                      const double *sr, double *inv_norm, double *pc, double *pr, double *hist,
+                      hipStream_t st) {
+    PowColOp<M, FOLD> oc;
+    oc.ci = T.ci;
+    oc.va = reinterpret_cast<const M *>(T.va);
+    oc.vg = vg; oc.inv_norm = inv_norm; oc.w = w; oc.sc = sc;
+    hipError_t e = run_pass(T, oc, pc, st);
+    if (e != hipSuccess) return e;
+    PowRowOp<M, FOLD> orw;
+    orw.ci = A.ci;
+    orw.va = reinterpret_cast<const M *>(A.va);
+    orw.w = w; orw.vg = vg; orw.sr = sr;
+    e = run_pass(A, orw, pr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_power_reduce, dim3(1), dim3(kWG), 0, st, pc, T.n_items + T.n_split,
+                       pr, A.n_items + A.n_split, hist, inv_norm);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- vector kernels
+
+template <class T> __global__ void k_fill(T *p, long long n, T v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+template <class D, class S> __global__ void k_copy(D *dst, const S *src, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (D)src[i];
+}
+template <class S>
+__global__ void k_scale_out(double *out, const S *v, const double *mul, double smul,
+                            long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = (mul ? mul[i] : smul) * (double)v[i];
+}
+template <class S>
+__global__ void k_xcur_out(double *out, const S *x0, const S *xh, double hx0, double hx1,
+                           const double *mul, double smul, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const S x = (S)hx0 * x0[i] + (S)hx1 * xh[i];
+        out[i] = (mul ? mul[i] : smul) * (double)x;
+    }
+}
+
+inline dim3 grid_for(long long n) {
+    long long g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return dim3((unsigned)g);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------- dispatch
+
+hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vs,
+                           const IterScalars &s, hipStream_t st) {
+    if (prec == 0) {
+        auto &v = *static_cast<const VecSet<double> *>(vs);
+        return keep ? col_pass<double, double, false, true>(T, v, s, st)
+                    : col_pass<double, double, false, false>(T, v, s, st);
+    }
+    if (prec == 1) {
+        auto &v = *static_cast<const VecSet<float> *>(vs);
+        return keep ? col_pass<float, float, true, true>(T, v, s, st)
+                    : col_pass<float, float, true, false>(T, v, s, st);
+    }
+    auto &v = *static_cast<const VecSet<double> *>(vs);
+    return keep ? col_pass<float, double, true, true>(T, v, s, st)
+                : col_pass<float, double, true, false>(T, v, s, st);
+}
+
+hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vs,
+                           const IterScalars &s, hipStream_t st) {
+    if (prec == 0) {
+        auto &v = *static_cast<const VecSet<double> *>(vs);
+        return keep ? row_pass<double, double, false, true>(A, v, s, st)
+                    : row_pass<double, double, false, false>(A, v, s, st);
+    }
+    if (prec == 1) {
+        auto &v = *static_cast<const VecSet<float> *>(vs);
+        return keep ? row_pass<float, float, true, true>(A, v, s, st)
+                    : row_pass<float, float, true, false>(A, v, s, st);
+    }
+    auto &v = *static_cast<const VecSet<double> *>(vs);
+    return keep ? row_pass<float, double, true, true>(A, v, s, st)
+                : row_pass<float, double, true, false>(A, v, s, st);
+}
+
+hipError_t launch_check_row(int prec, const DevMat &A, const void *vs, const CheckData &cd,
+                            const double *bd64, long long m1, double *parts, double *out,
+                            hipStream_t st) {
+    if (prec == 0)
+        return check_row<double, double>(A, *static_cast<const VecSet<double> *>(vs), cd, bd64,
+                                         m1, parts, out, st);
+    if (prec == 1)
+        return check_row<float, float>(A, *static_cast<const VecSet<float> *>(vs), cd, bd64, m1,
+                                       parts, out, st);
+    return check_row<float, double>(A, *static_cast<const VecSet<double> *>(vs), cd, bd64, m1,
+                                    parts, out, st);
+}
+
+hipError_t launch_check_col(int prec, const DevMat &T, const void *vs, const CheckData &cd,
+                            const double *cd64, const double *sc64, double *parts, double *out,
+                            hipStream_t st) {
+    if (prec == 0)
+        return check_col<double, double, false>(T, *static_cast<const VecSet<double> *>(vs), cd,
+                                                 cd64, nullptr, parts, out, st);
+    if (prec == 1)
+        return check_col<float, float, true>(T, *static_cast<const VecSet<float> *>(vs), cd, cd64,
+                                             sc64, parts, out, st);
+    return check_col<float, double, true>(T, *static_cast<const VecSet<double> *>(vs), cd, cd64,
+                                          sc64, parts, out, st);
+}
+
+hipError_t launch_power_iter(bool mat_f32, bool fold, const DevMat &A, const DevMat &T,
+                             double *vg, double *w, const double *sc, const double *sr,
+                             double *inv_norm, double *pc, double *pr, double *hist, int k,
+                             hipStream_t st) {
+    if (mat_f32) {
+        return fold ? power_iter<float, true>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st)
+                    : power_iter<float, false>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st);
+    }
+    return fold ? power_iter<double, true>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st)
+                : power_iter<double, false>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st);
+}
+
+hipError_t launch_fill(double *p, long long n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<double>, grid_for(n), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f(float *p, long long n, float v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<float>, grid_for(n), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_copy_d(double *dst, const double *src, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_copy<double, double>), grid_for(n), dim3(256), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+hipError_t launch_copy_f(float *dst, const float *src, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_copy<float, float>), grid_for(n), dim3(256), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+hipError_t launch_f2d(double *dst, const float *src, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_copy<double, float>), grid_for(n), dim3(256), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+hipError_t launch_scale_out(double *out, const void *v, bool v_f32, const double *mul,
+                            double smul, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (v_f32)
+        hipLaunchKernelGGL(k_scale_out<float>, grid_for(n), dim3(256), 0, st, out,
+                           static_cast<const float *>(v), mul, smul, n);
+    else
+        hipLaunchKernelGGL(k_scale_out<double>, grid_for(n), dim3(256), 0, st, out,
+                           static_cast<const double *>(v), mul, smul, n);
+    return hipGetLastError();
+}
+hipError_t launch_xcur_out(double *out, const void *x0, const void *xhat, bool v_f32,
+                           double hx0, double hx1, const double *mul, double smul, long long n,
+                           hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (v_f32)
+        hipLaunchKernelGGL(k_xcur_out<float>, grid_for(n), dim3(256), 0, st, out,
+                           static_cast<const float *>(x0), static_cast<const float *>(xhat),
+                           hx0, hx1, mul, smul, n);
+    else
+        hipLaunchKernelGGL(k_xcur_out<double>, grid_for(n), dim3(256), 0, st, out,
+                           static_cast<const double *>(x0), static_cast<const double *>(xhat),
+                           hx0, hx1, mul, smul, n);
+    return hipGetLastError();
+}
+
+}  // namespace hprlp

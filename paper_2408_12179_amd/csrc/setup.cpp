@@ -1,0 +1,225 @@
+// Host-side preprocessing of the HPR-LP library: input validation, the preconditioning of
+// Section 4.1 (Ruiz equilibration, a diagonal Pock-Chambolle pass with alpha = 1, b/c
+// normalisation), the CSR transpose, and the row-length tile schedules of the SpMV passes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "hprlp_setup.h"
+
+namespace hprlp {
+
+int validate_problem(int64_t m1, int64_t m2, int64_t n, const int64_t *rowptr,
+                     const int32_t *colidx, const double *val, const double *b,
+                     const double *c, const double *l, const double *u,
+                     const hprlp_options &o, std::string &err) {
+    if (!rowptr || !colidx || !val || !b || !c || !l || !u) {
+        err = "null input pointer";
+        return HPRLP_EINVAL;
+    }
+    if (m1 < 0 || m2 < 0 || m1 + m2 < 1 || n < 1 || m1 + m2 >= (1LL << 31) ||
+        n >= (1LL << 31)) {
+        err = "bad dimensions (need m1, m2 >= 0, m1 + m2 >= 1, n >= 1, both < 2^31)";
+        return HPRLP_EDIM;
+    }
+    const int64_t m = m1 + m2;
+    if (rowptr[0] != 0) {
+        err = "rowptr[0] must be 0";
+        return HPRLP_EDIM;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        if (rowptr[i + 1] < rowptr[i]) {
+            err = "rowptr is not non-decreasing at row " + std::to_string(i);
+            return HPRLP_EDIM;
+        }
+    const int64_t nnz = rowptr[m];
+    if (nnz < 1 || nnz >= (1LL << 31)) {
+        err = "nnz must be in [1, 2^31) (A must be non-zero)";
+        return HPRLP_EDIM;
+    }
+    std::vector<int64_t> seen((size_t)n, -1);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const int32_t j = colidx[p];
+            if (j < 0 || j >= n) {
+                err = "column index out of range in row " + std::to_string(i);
+                return HPRLP_EDIM;
+            }
+            if (seen[j] == i) {
+                err = "repeated column index in row " + std::to_string(i);
+                return HPRLP_EDIM;
+            }
+            seen[j] = i;
+        }
+    for (int64_t p = 0; p < nnz; ++p)
+        if (!std::isfinite(val[p])) {
+            err = "non-finite matrix value";
+            return HPRLP_ENONFINITE;
+        }
+    for (int64_t i = 0; i < m; ++i)
+        if (!std::isfinite(b[i])) {
+            err = "non-finite b";
+            return HPRLP_ENONFINITE;
+        }
+    for (int64_t j = 0; j < n; ++j) {
+        if (!std::isfinite(c[j])) {
+            err = "non-finite c";
+            return HPRLP_ENONFINITE;
+        }
+        if (std::isnan(l[j]) || std::isnan(u[j])) {
+            err = "NaN bound";
+            return HPRLP_ENONFINITE;
+        }
+        if (l[j] > u[j] || l[j] == INFINITY || u[j] == -INFINITY) {
+            err = "inconsistent bounds at column " + std::to_string(j);
+            return HPRLP_EBOUNDS;
+        }
+    }
+    if (o.precision == HPRLP_MIXED)
+        for (int64_t p = 0; p < nnz; ++p)
+            if ((double)(float)val[p] != val[p]) {
+                err = "MIXED precision needs every A value exactly representable in FP32";
+                return HPRLP_ENOTLOSSLESS;
+            }
+    return HPRLP_OK;
+}
+
+int validate_options(const hprlp_options &o, std::string &err) {
+    bool ok = o.tol > 0 && o.check_every >= 1 && o.max_iter >= 1 && o.alpha1 > 0 &&
+              o.alpha1 < 1 && o.alpha2 > 0 && o.alpha2 < 1 && o.alpha3 > 0 && o.alpha3 < 1 &&
+              o.sigma0 > 0 && o.ruiz_iters >= 0 && o.power_max_iter >= 1 && o.power_tol >= 0 &&
+              (o.precision == HPRLP_FP64 || o.precision == HPRLP_MIXED) && o.tol_switch > 0 &&
+              o.tile_nnz >= 256 && o.tile_rows >= 1 && o.tile_nnz + o.tile_rows <= 4096 &&
+              o.short_max >= 1 && o.short_max <= o.tile_nnz &&
+              o.split_len >= o.short_max && o.chunk_nnz >= 256;
+    if (!ok) err = "invalid option value";
+    return ok ? HPRLP_OK : HPRLP_EINVAL;
+}
+
+void resolve_options(hprlp_options &o) {
+    if (o.tile_nnz <= 0) o.tile_nnz = 2048;
+    if (o.tile_rows <= 0) o.tile_rows = 1024;
+    if (o.short_max <= 0) o.short_max = 256;
+    if (o.split_len <= 0) o.split_len = 8192;
+    if (o.chunk_nnz <= 0) o.chunk_nnz = 4096;
+}
+
+// Transpose of a CSR matrix by counting sort over the column index.  pos[q] is the position
+// in the original arrays of the q-th nonzero of the transpose (so any value array can be
+// permuted later).  Rows of the transpose list their columns in increasing order.
+void transpose(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *colidx,
+               std::vector<int64_t> &rowptr_t, std::vector<int32_t> &colidx_t,
+               std::vector<int32_t> &pos) {
+    const int64_t nnz = rowptr[m];
+    rowptr_t.assign((size_t)n + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) rowptr_t[(size_t)colidx[p] + 1]++;
+    for (int64_t j = 0; j < n; ++j) rowptr_t[j + 1] += rowptr_t[j];
+    std::vector<int64_t> fill(rowptr_t.begin(), rowptr_t.end() - 1);
+    colidx_t.resize((size_t)nnz);
+    pos.resize((size_t)nnz);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const int64_t q = fill[colidx[p]]++;
+            colidx_t[q] = (int32_t)i;
+            pos[q] = (int32_t)p;
+        }
+}
+
+// Preconditioning of Section 4.1 on A~ = D_r A D_c.  Each pass computes row factors from the
+// CSR rows and column factors from the rows of the transpose (same summation order as a
+// row-by-row scan), then rescales both copies.  Ruiz: sqrt of the infinity norms; the
+// Pock-Chambolle pass with alpha = 1: sqrt of the 1-norms.  Empty rows/columns keep 1.
+void precondition(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                  const std::vector<int64_t> &rowptr_t, const std::vector<int32_t> &pos,
+                  const double *val, const hprlp_options &o, Scaling &s) {
+    const int64_t nnz = rowptr[m];
+    s.val.assign(val, val + nnz);
+    std::vector<double> vt((size_t)nnz);
+    for (int64_t q = 0; q < nnz; ++q) vt[q] = val[pos[q]];
+    s.dr.assign((size_t)m, 1.0);
+    s.dc.assign((size_t)n, 1.0);
+    std::vector<double> rf((size_t)m), cf((size_t)n);
+    const int passes = o.ruiz_iters + (o.pock_chambolle ? 1 : 0);
+    for (int it = 0; it < passes; ++it) {
+        const bool ruiz = it < o.ruiz_iters;
+        for (int64_t i = 0; i < m; ++i) {
+            double acc = 0.0;
+            for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+                const double a = std::fabs(s.val[p]);
+                acc = ruiz ? std::max(acc, a) : acc + a;
+            }
+            rf[i] = acc > 0.0 ? std::sqrt(acc) : 1.0;
+        }
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int64_t q = rowptr_t[j]; q < rowptr_t[j + 1]; ++q) {
+                const double a = std::fabs(vt[q]);
+                acc = ruiz ? std::max(acc, a) : acc + a;
+            }
+            cf[j] = acc > 0.0 ? std::sqrt(acc) : 1.0;
+        }
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+                s.val[p] = s.val[p] / (rf[i] * cf[colidx[p]]);
+        for (int64_t q = 0; q < nnz; ++q) vt[q] = s.val[pos[q]];
+        for (int64_t i = 0; i < m; ++i) s.dr[i] = s.dr[i] / rf[i];
+        for (int64_t j = 0; j < n; ++j) s.dc[j] = s.dc[j] / cf[j];
+    }
+}
+
+void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &sp,
+                    const int32_t *inst_of_row, Schedule &out) {
+    out.items.clear();
+    out.splits.clear();
+    out.n_chunk_slots = 0;
+    out.tile_nnz = sp.tile_nnz;
+    out.tile_rows = sp.tile_rows;
+    std::vector<int4> tiles, longrows, chunks;
+    std::vector<std::pair<int64_t, int64_t>> longlen;  // (len, row) for ordering
+    auto inst = [&](int64_t r) { return inst_of_row ? inst_of_row[r] : 0; };
+    int64_t r0 = 0, tnnz = 0;
+    auto close_tile = [&](int64_t r1) {
+        if (r1 > r0) tiles.push_back(make_int4((int)r0, (int)r1, inst(r0), IT_TILE));
+        r0 = r1;
+        tnnz = 0;
+    };
+    for (int64_t r = 0; r < rows; ++r) {
+        const int64_t len = rowptr[r + 1] - rowptr[r];
+        const bool new_inst = inst_of_row && r > r0 && inst(r) != inst(r0);
+        if (len > sp.short_max) {
+            close_tile(r);
+            r0 = r + 1;
+            if (len <= sp.split_len) {
+                longlen.push_back({len, r});
+            } else {
+                const int nch = (int)((len + sp.chunk_nnz - 1) / sp.chunk_nnz);
+                out.splits.push_back(make_int4((int)r, out.n_chunk_slots, nch, inst(r)));
+                for (int c = 0; c < nch; ++c) {
+                    const int64_t p0 = rowptr[r] + (int64_t)c * sp.chunk_nnz;
+                    const int64_t p1 = std::min(rowptr[r + 1], p0 + sp.chunk_nnz);
+                    chunks.push_back(make_int4((int)p0, (int)p1, out.n_chunk_slots + c, IT_CHUNK));
+                }
+                out.n_chunk_slots += nch;
+            }
+            continue;
+        }
+        if (new_inst || tnnz + len > sp.tile_nnz || r - r0 >= sp.tile_rows) close_tile(r);
+        tnnz += len;
+    }
+    close_tile(rows);
+    std::stable_sort(longlen.begin(), longlen.end(),
+                     [](const std::pair<int64_t, int64_t> &a,
+                        const std::pair<int64_t, int64_t> &b) { return a.first > b.first; });
+    for (auto &lr : longlen)
+        longrows.push_back(make_int4((int)lr.second, inst(lr.second), 0, IT_ROW));
+    // heaviest work first so the tail of the launch is made of small tiles
+    out.items.reserve(chunks.size() + longrows.size() + tiles.size());
+    out.items.insert(out.items.end(), chunks.begin(), chunks.end());
+    out.items.insert(out.items.end(), longrows.begin(), longrows.end());
+    out.items.insert(out.items.end(), tiles.begin(), tiles.end());
+    out.n_tiles = (long long)tiles.size();
+    out.n_rowitems = (long long)longrows.size();
+    out.n_chunks = (long long)chunks.size();
+}
+
+}  // namespace hprlp

@@ -1,0 +1,156 @@
+"""The C ABI without a GPU: exported symbols, struct layouts, defaults and input validation
+(every validation error is returned before any HIP call, so these run on the CPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import lpgen
+from paper_2408_12179_amd import hprlp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hprlp.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hprlp.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hprlp_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "hprlp_create" in names and "hprlp_solve" in names and "hprlp_stats" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(hprlp.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    fields_o = [f for f, _ in hprlp.Options._fields_]
+    fields_s = [f if f != "lambda_" else "lambda" for f, _ in hprlp.Stats._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hprlp.h"', 'int main(void){',
+             'printf("%zu %zu\\n", sizeof(hprlp_options), sizeof(hprlp_stats_t));']
+    lines += [f'printf("%zu\\n", offsetof(hprlp_options, {f}));' for f in fields_o]
+    lines += [f'printf("%zu\\n", offsetof(hprlp_stats_t, {f}));' for f in fields_s]
+    lines += ["return 0;}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == C.sizeof(hprlp.Options) and out[1] == C.sizeof(hprlp.Stats)
+    offs = out[2:]
+    want = [getattr(hprlp.Options, f).offset for f in fields_o] + \
+           [getattr(hprlp.Stats, f if f != "lambda" else "lambda_").offset for f in fields_s]
+    assert offs == want
+
+
+def test_default_options_are_the_papers(lib):
+    o = hprlp.default_options()
+    assert o.tol == 1e-8 and o.check_every == 150
+    assert (o.alpha1, o.alpha2, o.alpha3) == (0.2, 0.6, 0.2)
+    assert o.sigma0 == 1.0 and o.ruiz_iters == 10 and o.pock_chambolle == 1
+    assert o.normalize_bc == 1 and o.use_halpern == 1 and o.use_restart == 1
+    assert o.sigma_update == 1 and o.precision == hprlp.FP64 and o.tol_switch == 1e-5
+    assert o.tile_nnz > 0 and o.split_len >= o.short_max
+
+
+def test_workspace_bytes(lib):
+    o = hprlp.default_options()
+    a = hprlp.workspace_bytes(50, 50, 200, 1000, o)
+    b = hprlp.workspace_bytes(500, 500, 2000, 10000, o)
+    assert 0 < a < b
+    o2 = hprlp.default_options(precision=hprlp.MIXED)
+    assert hprlp.workspace_bytes(500, 500, 2000, 10000, o2) > 0
+    with pytest.raises(hprlp.HPRLPError) as e:
+        hprlp.workspace_bytes(0, 0, 10, 10, o)
+    assert e.value.code == hprlp.EDIM
+
+
+def _create(lib, lp, ws=256, **opt):
+    o = hprlp.default_options(**opt)
+    arrs = [np.ascontiguousarray(lp.rowptr, dtype=np.int64),
+            np.ascontiguousarray(lp.colidx, dtype=np.int32)] + \
+        [np.ascontiguousarray(a, dtype=np.float64) for a in (lp.val, lp.b, lp.c, lp.l, lp.u)]
+    h = C.c_void_p()
+    rc = lib.hprlp_create(C.byref(h), lp.m1, lp.m2, lp.n, *[C.c_void_p(a.ctypes.data) for a in arrs],
+                          C.byref(o), C.c_void_p(ws), 1 << 30, None)
+    return rc, lib.hprlp_last_error(None).decode()
+
+
+def _bad(mutate):
+    lp = lpgen.make("c0")
+    lp = lpgen.LP(lp.name, lp.m1, lp.m2, lp.n, lp.rowptr.copy(), lp.colidx.copy(), lp.val.copy(),
+                  lp.b.copy(), lp.c.copy(), lp.l.copy(), lp.u.copy())
+    mutate(lp)
+    return lp
+
+
+@pytest.mark.parametrize("case,code", [
+    ("empty_rows", hprlp.EDIM),
+    ("rowptr_not_monotone", hprlp.EDIM),
+    ("col_out_of_range", hprlp.EDIM),
+    ("repeated_col", hprlp.EDIM),
+    ("nan_in_A", hprlp.ENONFINITE),
+    ("inf_in_b", hprlp.ENONFINITE),
+    ("nan_bound", hprlp.ENONFINITE),
+    ("l_gt_u", hprlp.EBOUNDS),
+    ("l_plus_inf", hprlp.EBOUNDS),
+    ("not_fp32_exact", hprlp.ENOTLOSSLESS),
+    ("bad_option", hprlp.EINVAL),
+    ("misaligned_workspace", hprlp.EINVAL),
+    ("null_workspace", hprlp.EINVAL),
+])
+def test_create_rejects_bad_input_before_any_gpu_call(lib, case, code):
+    opt, ws = {}, 256
+    if case == "empty_rows":
+        lp = _bad(lambda p: None)
+        lp.m1, lp.m2 = 0, 0
+        lp.rowptr = lp.rowptr[:1]
+    elif case == "rowptr_not_monotone":
+        lp = _bad(lambda p: p.rowptr.__setitem__(3, p.rowptr[4] + 1))
+    elif case == "col_out_of_range":
+        lp = _bad(lambda p: p.colidx.__setitem__(5, p.n))
+    elif case == "repeated_col":
+        lp = _bad(lambda p: p.colidx.__setitem__(p.rowptr[0] + 1, p.colidx[p.rowptr[0]]))
+    elif case == "nan_in_A":
+        lp = _bad(lambda p: p.val.__setitem__(7, np.nan))
+    elif case == "inf_in_b":
+        lp = _bad(lambda p: p.b.__setitem__(2, np.inf))
+    elif case == "nan_bound":
+        lp = _bad(lambda p: p.u.__setitem__(2, np.nan))
+    elif case == "l_gt_u":
+        lp = _bad(lambda p: (p.l.__setitem__(4, 5.0), p.u.__setitem__(4, 1.0)))
+    elif case == "l_plus_inf":
+        lp = _bad(lambda p: (p.l.__setitem__(4, np.inf), p.u.__setitem__(4, np.inf)))
+    elif case == "not_fp32_exact":
+        lp = _bad(lambda p: p.val.__setitem__(0, 0.1))
+        opt = dict(precision=hprlp.MIXED)
+    elif case == "bad_option":
+        lp = _bad(lambda p: None)
+        opt = dict(tol=0.0)
+    elif case == "misaligned_workspace":
+        lp = _bad(lambda p: None)
+        ws = 257
+    else:
+        lp = _bad(lambda p: None)
+        ws = 0
+    rc, msg = _create(lib, lp, ws=ws, **opt)
+    assert rc == code, (rc, msg)
+    assert msg
+
+
+def test_null_out_pointer(lib):
+    o = hprlp.default_options()
+    rc = lib.hprlp_create(None, 1, 0, 1, None, None, None, None, None, None, None, C.byref(o),
+                          None, 0, None)
+    assert rc == hprlp.EINVAL
