@@ -86,7 +86,11 @@ typedef struct {
     int short_max;           /* schedule: longest row kept in tiles (0 = default)          */
     int split_len;           /* schedule: rows longer than this are split (0 = default)    */
     int chunk_nnz;           /* schedule: nonzeros per split chunk (0 = default)           */
-    int profile;             /* 1: time every pass launch with HIP events (stats)          */
+    int reorder;             /* 1 (default): number the columns by decreasing nonzero count */
+                             /* inside the library (denser gather cache lines); results    */
+                             /* are returned in the caller's order either way              */
+    int profile;             /* N > 0: time the passes of every N-th iteration with HIP    */
+                             /* events (stats col/row_pass_ms); 0: off                     */
     int verbose;             /* 1: one log line per check on stderr                        */
 } hprlp_options;
 
@@ -103,8 +107,10 @@ typedef struct {
     double t_power_ms;       /* power method (counted in the solve time, Section 4.1)      */
     double t_solve_ms;       /* whole solve incl. power method; excludes create            */
     double bytes_per_iter;   /* algorithmic HBM bytes of one iteration in the final phase  */
-    double col_pass_ms, row_pass_ms;   /* profile=1: summed kernel time of each pass        */
+    double col_pass_ms, row_pass_ms;   /* profile=1: summed time of the main SpMV kernel of  */
+                                       /* the column (x-step) and row (y-step) passes       */
     long long col_pass_launches, row_pass_launches;
+    double split_ms;         /* profile=1: summed time of the split-row finishing kernels  */
     long long n_checks;
 } hprlp_stats_t;
 

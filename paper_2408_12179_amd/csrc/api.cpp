@@ -61,6 +61,7 @@ struct hprlp_handle {
     VecSet<float> v32;
     CheckData chk;
     double *ux = nullptr, *uy = nullptr;     // unscaling of x and y (FP64 mode: vectors)
+    int *cperm = nullptr;                   // column renumbering: internal j -> caller's column
     double *vg = nullptr, *w = nullptr, *hist = nullptr, *inv_norm = nullptr;
     double *partsA = nullptr, *partsT = nullptr;
     double *res = nullptr;                  // [4][kNQ]
@@ -140,6 +141,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     c.co = cv.arr<double>(n); c.cs = cv.arr<double>(n); c.xs = cv.arr<double>(n);
     c.lo = cv.arr<double>(n); c.uo = cv.arr<double>(n);
     double *ux = cv.arr<double>(n), *uy = cv.arr<double>(m);
+    int *cperm = cv.arr<int>(n);
     double *vg = cv.arr<double>(m), *w = cv.arr<double>(n);
     double *hist = cv.arr<double>((size_t)p.power_cap);
     double *inv_norm = cv.arr<double>(1);
@@ -153,6 +155,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         h->T.rp = T.rp; h->T.ci = T.ci; h->T.va = T.va; h->T.items = T.items;
         h->T.splits = T.splits; h->T.split_part = T.split_part;
         h->v64 = d; h->v32 = f; h->chk = c; h->ux = ux; h->uy = uy; h->vg = vg; h->w = w;
+        h->cperm = cperm;
         h->hist = hist; h->inv_norm = inv_norm; h->partsA = partsA; h->partsT = partsT;
         h->res = res; h->outv = outv;
     }
@@ -172,8 +175,9 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o) {
     Plan p;
     p.m = m; p.n = n; p.nnz = nnz; p.mixed = o.precision == HPRLP_MIXED;
     const int64_t ch = nnz / o.chunk_nnz + 1;
-    p.itemsA = (int)std::min<int64_t>(2 * m + ch, INT32_MAX / 8);
-    p.itemsT = (int)std::min<int64_t>(2 * n + ch, INT32_MAX / 8);
+    // + 3 * kXCD padding items (one partial class of each kind)
+    p.itemsA = (int)std::min<int64_t>(2 * m + ch + 3 * kXCD, INT32_MAX / 8);
+    p.itemsT = (int)std::min<int64_t>(2 * n + ch + 3 * kXCD, INT32_MAX / 8);
     p.splitA = (int)std::min<int64_t>(m, nnz / o.split_len + 1);
     p.splitT = (int)std::min<int64_t>(n, nnz / o.split_len + 1);
     p.slotsA = (int)ch + p.splitA;
@@ -210,7 +214,7 @@ int create_device(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
                   const double *u, const std::vector<int64_t> &rpt,
                   const std::vector<int32_t> &cit, const std::vector<int32_t> &pos,
                   const Scaling &sc, const std::vector<double> &bs,
-                  const std::vector<double> &cs) {
+                  const std::vector<double> &cs, const std::vector<int32_t> &order) {
     const hprlp_options &o = h->opt;
     const int64_t m = h->m, n = h->n, nnz = h->nnz;
     const double bb = h->beta_b, bc = h->beta_c;
@@ -224,6 +228,7 @@ int create_device(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
         if ((rc = upload(h, h->T.rp, rp32.data(), (size_t)n + 1))) return rc;
         HIPCHK(h, hipStreamSynchronize(h->st));
     }
+    if ((rc = upload(h, h->cperm, order.data(), (size_t)n))) return rc;
     if ((rc = upload(h, h->A.ci, colidx, (size_t)nnz))) return rc;
     if ((rc = upload(h, h->T.ci, cit.data(), (size_t)nnz))) return rc;
     if (h->mixed) {
@@ -350,6 +355,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->sigma_update = 1;
     o->precision = HPRLP_FP64;
     o->tol_switch = 1e-5;
+    o->reorder = 1;
     o->profile = 0;
     o->verbose = 0;
     resolve_options(*o);
@@ -398,13 +404,54 @@ extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t 
     h->st = static_cast<hipStream_t>(stream);
 
     // ---- host preprocessing
+    // Column renumbering by decreasing nonzero count: the most gathered entries of x_hat
+    // then share cache lines.  It permutes the variables only; every output is scattered
+    // back to the caller's order.
+    std::vector<int32_t> order((size_t)n), colr;
+    std::vector<double> valr, cr, lr, ur;
+    for (int64_t j = 0; j < n; ++j) order[j] = (int32_t)j;
+    if (o.reorder) {
+        std::vector<int64_t> deg((size_t)n, 0);
+        for (int64_t p = 0; p < nnz; ++p) deg[colidx[p]]++;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b2) { return deg[a] > deg[b2]; });
+        std::vector<int32_t> inv((size_t)n);
+        for (int64_t j = 0; j < n; ++j) inv[order[j]] = (int32_t)j;
+        colr.resize((size_t)nnz);
+        valr.resize((size_t)nnz);
+        std::vector<std::pair<int32_t, double>> rowbuf;
+        for (int64_t i = 0; i < m; ++i) {
+            rowbuf.clear();
+            for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+                rowbuf.push_back({inv[colidx[p]], val[p]});
+            std::sort(rowbuf.begin(), rowbuf.end(),
+                      [](const std::pair<int32_t, double> &a,
+                         const std::pair<int32_t, double> &b2) { return a.first < b2.first; });
+            for (size_t q = 0; q < rowbuf.size(); ++q) {
+                colr[rowptr[i] + q] = rowbuf[q].first;
+                valr[rowptr[i] + q] = rowbuf[q].second;
+            }
+        }
+        cr.resize((size_t)n); lr.resize((size_t)n); ur.resize((size_t)n);
+        for (int64_t j = 0; j < n; ++j) {
+            cr[j] = c[order[j]];
+            lr[j] = l[order[j]];
+            ur[j] = u[order[j]];
+        }
+        colidx = colr.data();
+        val = valr.data();
+        c = cr.data();
+        l = lr.data();
+        u = ur.data();
+    }
     std::vector<int64_t> rpt;
     std::vector<int32_t> cit, pos;
     transpose(m, n, rowptr, colidx, rpt, cit, pos);
     Scaling sc;
     precondition(m, n, rowptr, colidx, rpt, pos, val, o, sc);
     h->dr = sc.dr;
-    h->dc = sc.dc;
+    h->dc.assign((size_t)n, 1.0);
+    for (int64_t j = 0; j < n; ++j) h->dc[order[j]] = sc.dc[j];  // caller's column order
     std::vector<double> bs((size_t)m), cs((size_t)n);
     for (int64_t i = 0; i < m; ++i) bs[i] = sc.dr[i] * b[i];
     for (int64_t j = 0; j < n; ++j) cs[j] = sc.dc[j] * c[j];
@@ -451,7 +498,7 @@ extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t 
     h->A.rows = (int)m;
     h->T.rows = (int)n;
 
-    rc = create_device(h, rowptr, colidx, val, b, c, l, u, rpt, cit, pos, sc, bs, cs);
+    rc = create_device(h, rowptr, colidx, val, b, c, l, u, rpt, cit, pos, sc, bs, cs, order);
     if (rc) {
         g_create_error = h->err;
         hprlp_destroy(h);
@@ -483,7 +530,7 @@ const void *cur_set(const hprlp_handle *h) {
 }
 
 struct ProfRec {
-    size_t ev0;
+    size_t ev0;  // events ev0 (before), ev0+1 (after the main kernel), ev0+2 (after finisher)
     bool col;
 };
 
@@ -493,17 +540,18 @@ int run_iteration(hprlp_handle *h, bool keep, std::vector<ProfRec> *prof, size_t
     fill_scalars(h, s);
     const void *vs = cur_set(h);
     for (int pass = 0; pass < 2; ++pass) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr;
         if (prof) {
             e0 = pool_event(h, *ev_next);
-            e1 = pool_event(h, *ev_next + 1);
-            if (!e0 || !e1) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
+            em = pool_event(h, *ev_next + 1);
+            e1 = pool_event(h, *ev_next + 2);
+            if (!e0 || !em || !e1) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
             prof->push_back({*ev_next, pass == 0});
-            *ev_next += 2;
+            *ev_next += 3;
             HIPCHK(h, hipEventRecord(e0, h->st));
         }
-        hipError_t e = pass == 0 ? launch_col_pass(h->prec, keep, h->T, vs, s, h->st)
-                                 : launch_row_pass(h->prec, keep, h->A, vs, s, h->st);
+        hipError_t e = pass == 0 ? launch_col_pass(h->prec, keep, h->T, vs, s, h->st, em)
+                                 : launch_row_pass(h->prec, keep, h->A, vs, s, h->st, em);
         if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("pass launch: ") + hipGetErrorString(e));
         if (prof) HIPCHK(h, hipEventRecord(e1, h->st));
     }
@@ -669,14 +717,16 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     std::vector<ProfRec> prof;
     size_t ev_next = 0;
     std::vector<ProfRec> *pp = o.profile ? &prof : nullptr;
-    double prof_ms[2] = {0, 0};
+    double prof_ms[2] = {0, 0}, split_ms = 0;
     long long prof_n[2] = {0, 0};
     auto flush_prof = [&]() -> int {
         for (auto &p : prof) {
-            float ms = 0;
+            float ms = 0, ms2 = 0;
             HIPCHK(h, hipEventElapsedTime(&ms, h->ev_pool[p.ev0], h->ev_pool[p.ev0 + 1]));
+            HIPCHK(h, hipEventElapsedTime(&ms2, h->ev_pool[p.ev0 + 1], h->ev_pool[p.ev0 + 2]));
             prof_ms[p.col ? 0 : 1] += ms;
             prof_n[p.col ? 0 : 1] += 1;
+            split_ms += ms2;
         }
         prof.clear();
         ev_next = 0;
@@ -695,11 +745,14 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
         if (!first && !chk) {
             const long long next_check = ((h->k / ce) + 1) * ce;
             const long long last = std::min(next_check, o.max_iter) - 1;
-            while (h->k + 1 <= last)
-                if ((rc = run_iteration(h, false, pp, &ev_next))) return rc;
+            while (h->k + 1 <= last) {
+                // profile = N: bracket every N-th iteration's passes with HIP events
+                const bool samp = pp && (h->k % o.profile) == 0;
+                if ((rc = run_iteration(h, false, samp ? pp : nullptr, &ev_next))) return rc;
+            }
             continue;
         }
-        if ((rc = run_iteration(h, true, pp, &ev_next))) return rc;
+        if ((rc = run_iteration(h, true, nullptr, &ev_next))) return rc;
         if (h->prec == 1) iters_fp32 = h->k;
         if ((rc = run_check(h, chk ? 1 : 0))) return rc;
         if (!chk) {
@@ -789,9 +842,9 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     const void *yb = f32 ? (const void *)h->v32.ybar : (const void *)h->v64.ybar;
     const void *zb = f32 ? (const void *)h->v32.zint : (const void *)h->v64.zint;
     double *ox = h->outv, *oy = h->outv + h->n, *oz = h->outv + h->n + h->m;
-    hipError_t e = launch_scale_out(ox, xb, f32, h->ux, 0.0, h->n, h->st);
-    if (e == hipSuccess) e = launch_scale_out(oy, yb, f32, h->uy, 0.0, h->m, h->st);
-    if (e == hipSuccess) e = launch_scale_out(oz, zb, f32, h->chk.co, 0.0, h->n, h->st);
+    hipError_t e = launch_scale_out(ox, xb, f32, h->ux, 0.0, h->cperm, h->n, h->st);
+    if (e == hipSuccess) e = launch_scale_out(oy, yb, f32, h->uy, 0.0, nullptr, h->m, h->st);
+    if (e == hipSuccess) e = launch_scale_out(oz, zb, f32, h->chk.co, 0.0, h->cperm, h->n, h->st);
     if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
     HIPCHK(h, hipStreamSynchronize(h->st));
     const double t_end = now_ms();
@@ -818,6 +871,7 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     s.row_pass_ms = prof_ms[1];
     s.col_pass_launches = prof_n[0];
     s.row_pass_launches = prof_n[1];
+    s.split_ms = split_ms;
     s.n_checks = (long long)h->trace.size();
     if (status) *status = st_out;
     return HPRLP_OK;
@@ -844,15 +898,15 @@ extern "C" int hprlp_get_iterate(const hprlp_handle *hc, int which, double *out)
     long long len = 0;
     switch (which) {
     case HPRLP_XBAR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.xbar : h->v64.xbar, f32, h->ux, 0, h->n, h->st);
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.xbar : h->v64.xbar, f32, h->ux, 0, h->cperm, h->n, h->st);
         len = h->n;
         break;
     case HPRLP_YBAR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.ybar : h->v64.ybar, f32, h->uy, 0, h->m, h->st);
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.ybar : h->v64.ybar, f32, h->uy, 0, nullptr, h->m, h->st);
         len = h->m;
         break;
     case HPRLP_ZBAR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.zint : h->v64.zint, f32, h->chk.co, 0, h->n, h->st);
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.zint : h->v64.zint, f32, h->chk.co, 0, h->cperm, h->n, h->st);
         len = h->n;
         break;
     case HPRLP_XCUR: {
@@ -860,12 +914,12 @@ extern "C" int hprlp_get_iterate(const hprlp_handle *hc, int which, double *out)
         fill_scalars(h, s);
         e = launch_xcur_out(tmp, f32 ? (const void *)h->v32.x0 : h->v64.x0,
                             f32 ? (const void *)h->v32.xhat : h->v64.xhat, f32, s.hx0, s.hx1,
-                            h->ux, 0, h->n, h->st);
+                            h->ux, 0, h->cperm, h->n, h->st);
         len = h->n;
         break;
     }
     case HPRLP_YCUR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.y : h->v64.y, f32, h->uy, 0, h->m, h->st);
+        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.y : h->v64.y, f32, h->uy, 0, nullptr, h->m, h->st);
         len = h->m;
         break;
     default:

@@ -16,12 +16,17 @@ constexpr int kWG = 256;          // threads per workgroup of the SpMV passes (4
 constexpr int kNQ = 6;            // check quantities per pass (row pass and column pass)
 
 // Work-item kinds of a pass schedule.  One workgroup processes one item.
-enum ItemKind : int { IT_TILE = 0, IT_ROW = 1, IT_CHUNK = 2 };
+enum ItemKind : int { IT_TILE = 0, IT_ROW = 1, IT_CHUNK = 2, IT_EMPTY = 3 };
+constexpr int kXCD = 8;           // accelerator complex dies of an MI355X
+constexpr int kMaxTileNnz = 2048; // kWG threads x 8 nonzeros (kernels.hip, kEPT)
+constexpr int kMaxTileRows = 1024;// kWG threads x 4 rows (kernels.hip, kRPT)
 
-// Schedule of one CSR matrix (host side, then uploaded).
-//   TILE : {r0, r1, inst, IT_TILE}   rows [r0, r1), all short, nnz <= tile_nnz
-//   ROW  : {r, inst, 0, IT_ROW}      one long row, whole workgroup
-//   CHUNK: {p0, p1, slot, IT_CHUNK}  a piece of a split row; partial sum -> split_part[slot]
+// Schedule of one CSR matrix (host side, then uploaded).  The kind is in the low 2 bits of w.
+//   TILE : {r0, P0, inst, nrows << 14 | cnt << 2 | IT_TILE}  rows [r0, r0+nrows), all short,
+//          nonzeros [P0, P0+cnt) with cnt <= tile_nnz <= 2048, nrows <= tile_rows <= 1024
+//   ROW  : {r, P0, P1, inst << 2 | IT_ROW}     one long row, whole workgroup
+//   CHUNK: {p0, p1, slot, IT_CHUNK}            piece of a split row; partial -> split_part[slot]
+//   EMPTY: {0, 0, 0, IT_EMPTY}                 padding so each class starts on an XCD boundary
 // splits: {row, slot0, nslots, inst} finished (fixed-order sum + epilogue) by a second kernel.
 struct Schedule {
     std::vector<int4> items;
@@ -84,10 +89,11 @@ struct CheckData {
 // ---------------------------------------------------------------- kernel launchers
 // prec: 0 = FP64 (double A, double vectors, no fold); 1 = MIXED FP32 phase (float A, float
 // vectors, fold); 2 = MIXED FP64 phase (float A, double vectors, fold).
+// ev_mid (nullable): recorded between the main SpMV kernel and the split-row finisher
 hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vecset,
-                           const IterScalars &s, hipStream_t st);
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev_mid = nullptr);
 hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vecset,
-                           const IterScalars &s, hipStream_t st);
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev_mid = nullptr);
 // check passes: write kNQ partial sums per slot into parts, then reduce into out[kNQ]
 // bd64 / cd64 / sc64: FP64 right-hand side, cost and folded column scaling (dc^2, MIXED only)
 hipError_t launch_check_row(int prec, const DevMat &A, const void *vecset, const CheckData &cd,
@@ -107,12 +113,13 @@ hipError_t launch_fill_f(float *p, long long n, float v, hipStream_t st);
 hipError_t launch_copy_d(double *dst, const double *src, long long n, hipStream_t st);
 hipError_t launch_copy_f(float *dst, const float *src, long long n, hipStream_t st);
 hipError_t launch_f2d(double *dst, const float *src, long long n, hipStream_t st);
-// out = mul[i] * v[i] (mul == nullptr -> scalar smul); v in float or double
+// out[perm[i]] = mul[i] * v[i] (mul == nullptr -> scalar smul; perm == nullptr -> identity);
+// v in float or double
 hipError_t launch_scale_out(double *out, const void *v, bool v_f32, const double *mul,
-                            double smul, long long n, hipStream_t st);
-// x^{r,t} = hx0 * x0 + hx1 * xhat, scaled by mul/smul
+                            double smul, const int *perm, long long n, hipStream_t st);
+// x^{r,t} = hx0 * x0 + hx1 * xhat, scaled by mul/smul, scattered by perm
 hipError_t launch_xcur_out(double *out, const void *x0, const void *xhat, bool v_f32,
-                           double hx0, double hx1, const double *mul, double smul, long long n,
-                           hipStream_t st);
+                           double hx0, double hx1, const double *mul, double smul,
+                           const int *perm, long long n, hipStream_t st);
 
 }  // namespace hprlp

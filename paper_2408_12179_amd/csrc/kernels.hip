@@ -16,6 +16,9 @@
 //   ROW    one long row summed by the whole workgroup (wavefront shuffles + LDS).
 //   CHUNK  a slice of a very long row; its partial sum goes to a slot and a second small
 //          kernel adds the slots of each split row in index order and runs the epilogue.
+// The host lays the items out XCD-aware: workgroup b runs on XCD b % 8, and each item class
+// is interleaved so that every XCD walks a contiguous range of it (rows that share gathered
+// cache lines stay on one XCD's L2) while all XCDs see the same mix of heavy and light work.
 // Check passes (every check_every iterations) reuse the same kernel with epilogues that
 // produce per-workgroup partial sums of the termination / restart / sigma quantities,
 // reduced by a single-workgroup kernel in a fixed order.
@@ -68,61 +71,139 @@ template <class M, class V> struct AccT { using type = double; };
 template <> struct AccT<float, float> { using type = float; };
 
 // ------------------------------------------------------------------------- the SpMV kernel
+//
+// Op interface (one per pass kind):
+//   Raw raw(p)               nonzero p: column index and value, loaded with a streaming hint
+//   Sum prod(const Raw&)     gather of the input vector(s) and product
+//   Pre load(row)            epilogue operands of one row (prefetched when PREFETCH)
+//   void apply(row, sum, pre, inst, q)   the fused epilogue; q accumulates check terms
+// Loads are issued in batches of kEPT per thread (all indices/values first, then all
+// gathers) so each workgroup pays two memory latencies per batch instead of one per element.
+
+constexpr int kEPT = 8;   // nonzeros per thread per batch (tile_nnz <= kWG * kEPT)
+constexpr int kRPT = 4;   // rows per thread in the tile epilogue (tile_rows <= kWG * kRPT)
+
+template <class M> struct RawT {
+    int j;
+    M a;
+};
+template <class M>
+__device__ __forceinline__ RawT<M> load_raw(const int *__restrict__ ci, const M *__restrict__ va,
+                                            int p) {
+    return RawT<M>{__builtin_nontemporal_load(ci + p), __builtin_nontemporal_load(va + p)};
+}
+
+struct NoPre {};
+
+// Sum of op.prod over nonzeros [b, e) by the whole workgroup (e > b).  The batch is
+// branch-free: out-of-range lanes re-load the last nonzero (a cache hit) and contribute zero
+// through a select, so all kEPT index/value loads and then all kEPT gathers are in flight
+// together.
+template <class Op>
+__device__ __forceinline__ typename Op::Sum row_sum(const Op &op, int b, int e, int tid) {
+    using S = typename Op::Sum;
+    S s = szero<S>();
+    for (int base = b; base < e; base += kWG * kEPT) {
+        typename Op::Raw raw[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) raw[u] = op.raw(min(base + tid + u * kWG, e - 1));
+        S v[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) v[u] = op.prod(raw[u]);
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) s = s + (base + tid + u * kWG < e ? v[u] : szero<S>());
+    }
+    return s;
+}
 
 template <class Op>
 __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
                                               const int *__restrict__ rp, Op op,
                                               typename Op::Sum *__restrict__ split_part,
-                                              double *__restrict__ parts) {
+                                              double *__restrict__ parts, int tile_cap,
+                                              int rows_cap) {
     using S = typename Op::Sum;
+    using Pre = typename Op::Pre;
     constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ S red[4];
     __shared__ double redq[4];
     const int4 it = items[blockIdx.x];
+    const int kind = it.w & 3;
     const int tid = threadIdx.x;
     double q[NQ];
 #pragma unroll
     for (int j = 0; j < NQ; ++j) q[j] = 0.0;
 
-    if (it.w == IT_TILE) {
+    if (kind == IT_TILE) {
         S *prod = reinterpret_cast<S *>(smem);
-        S *rsum = prod + op.tile_nnz;
-        const int r0 = it.x, r1 = it.y, inst = it.z;
-        const int P0 = rp[r0];
-        const int cnt = rp[r1] - P0;
-#pragma unroll 4
-        for (int k = tid; k < cnt; k += kWG) prod[k] = op.prod(P0 + k);
+        S *rsum = prod + tile_cap;
+        int *rpl = reinterpret_cast<int *>(rsum + rows_cap);
+        const int r0 = it.x, P0 = it.y, inst = it.z;
+        const int nrows = it.w >> 14, cnt = (it.w >> 2) & 4095;
+        const int r1 = r0 + nrows;
+        Pre pre[kRPT];
+        if constexpr (Op::PREFETCH) {
+            // rows past the tile re-load the tile's last row (valid, unused)
+#pragma unroll
+            for (int u = 0; u < kRPT; ++u) pre[u] = op.load(min(r0 + tid + u * kWG, r1 - 1));
+        }
+        // the tile's row pointers, staged in LDS for phase 2
+        int rpv[kRPT];
+#pragma unroll
+        for (int u = 0; u < kRPT; ++u) rpv[u] = rp[min(r0 + tid + u * kWG, r1 - 1)];
+        if (cnt > 0) {  // uniform: a tile of empty rows has no nonzeros to stream
+            typename Op::Raw raw[kEPT];
+#pragma unroll
+            for (int u = 0; u < kEPT; ++u) raw[u] = op.raw(P0 + min(tid + u * kWG, cnt - 1));
+            S v[kEPT];
+#pragma unroll
+            for (int u = 0; u < kEPT; ++u) v[u] = op.prod(raw[u]);
+#pragma unroll
+            for (int u = 0; u < kEPT; ++u) {
+                const int k = tid + u * kWG;
+                if (k < cnt) prod[k] = v[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRPT; ++u) {
+            const int rr = tid + u * kWG;
+            if (rr < nrows) rpl[rr] = rpv[u] - P0;
+        }
+        if (tid == 0) rpl[nrows] = cnt;
         __syncthreads();
-        const int nrows = r1 - r0;
         int G = 1;
         while (G < 64 && 2 * G * nrows <= kWG) G <<= 1;
         const int lg = tid & (G - 1);
         const int ng = kWG / G;
         for (int rr = tid / G; rr < nrows; rr += ng) {
-            const int b = rp[r0 + rr] - P0, e = rp[r0 + rr + 1] - P0;
+            const int b = rpl[rr], e = rpl[rr + 1];
             S s = szero<S>();
             for (int k = b + lg; k < e; k += G) s = s + prod[k];
             for (int off = G >> 1; off > 0; off >>= 1) s = s + xshfl(s, off);
             if (lg == 0) rsum[rr] = s;
         }
         __syncthreads();
-        for (int rr = tid; rr < nrows; rr += kWG) op.epilogue(r0 + rr, rsum[rr], inst, q);
-    } else if (it.w == IT_ROW) {
-        const int r = it.x, inst = it.y;
-        const int b = rp[r], e = rp[r + 1];
-        S s = szero<S>();
-#pragma unroll 4
-        for (int k = b + tid; k < e; k += kWG) s = s + op.prod(k);
+#pragma unroll
+        for (int u = 0; u < kRPT; ++u) {
+            const int rr = tid + u * kWG;
+            if (rr < nrows) {
+                if constexpr (Op::PREFETCH) op.apply(r0 + rr, rsum[rr], pre[u], inst, q);
+                else op.apply(r0 + rr, rsum[rr], op.load(r0 + rr), inst, q);
+            }
+        }
+    } else if (kind == IT_ROW) {
+        const int r = it.x, inst = it.w >> 2;
+        Pre pre{};
+        if (Op::PREFETCH && tid == 0) pre = op.load(r);
+        S s = row_sum(op, it.y, it.z, tid);
         s = block_sum(s, red);
-        if (tid == 0) op.epilogue(r, s, inst, q);
-    } else {
-        S s = szero<S>();
-#pragma unroll 4
-        for (int k = it.x + tid; k < it.y; k += kWG) s = s + op.prod(k);
+        if (tid == 0) op.apply(r, s, Op::PREFETCH ? pre : op.load(r), inst, q);
+    } else if (kind == IT_CHUNK) {
+        S s = row_sum(op, it.x, it.y, tid);
         s = block_sum(s, red);
         if (tid == 0) split_part[it.z] = s;
-    }
+    }  // IT_EMPTY: padding item, only the (zero) check partials below
     if constexpr (Op::NQ > 0) {
 #pragma unroll
         for (int j = 0; j < Op::NQ; ++j) {
@@ -147,7 +228,7 @@ __global__ __launch_bounds__(64) void k_split(const int4 *__restrict__ splits,
         double q[NQ];
 #pragma unroll
         for (int j = 0; j < NQ; ++j) q[j] = 0.0;
-        op.epilogue(sp.x, s, sp.w, q);
+        op.apply(sp.x, s, op.load(sp.x), sp.w, q);
         if constexpr (Op::NQ > 0) {
 #pragma unroll
             for (int j = 0; j < Op::NQ; ++j)
@@ -156,14 +237,28 @@ __global__ __launch_bounds__(64) void k_split(const int4 *__restrict__ splits,
     }
 }
 
+constexpr int kRedWG = 1024;
+
+// Sum over a 1024-thread workgroup (16 wavefronts); valid in thread 0.
+__device__ __forceinline__ double block_sum_1024(double v, double *red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kRedWG / 64; ++w) t += red[w];
+    return t;
+}
+
 // Fixed-order reduction of per-workgroup partials: out[j] = sum_k parts[k*nq + j].
-__global__ __launch_bounds__(kWG) void k_reduce(const double *__restrict__ parts, int nslots,
-                                                int nq, double *__restrict__ out) {
-    __shared__ double red[4];
+__global__ __launch_bounds__(kRedWG) void k_reduce(const double *__restrict__ parts, int nslots,
+                                                   int nq, double *__restrict__ out) {
+    __shared__ double red[kRedWG / 64];
     for (int j = 0; j < nq; ++j) {
         double s = 0.0;
-        for (int k = threadIdx.x; k < nslots; k += kWG) s += parts[(size_t)k * nq + j];
-        s = block_sum(s, red);
+        for (int k = threadIdx.x; k < nslots; k += kRedWG) s += parts[(size_t)k * nq + j];
+        s = block_sum_1024(s, red);
         if (threadIdx.x == 0) out[j] = s;
     }
 }
@@ -177,8 +272,12 @@ __global__ __launch_bounds__(kWG) void k_reduce(const double *__restrict__ parts
 //   keep:  x_bar, z_int = (x_bar - v)/sigma (eq. update-z), dx = x - x_hat
 template <class M, class V, bool FOLD, bool KEEP> struct ColOp {
     using Sum = typename AccT<M, V>::type;
+    using Raw = RawT<M>;
     static constexpr int NQ = 0;
-    int tile_nnz;
+    static constexpr bool PREFETCH = true;
+    struct Pre {
+        V xh, x0, cd, ld, ud, sc;
+    };
     const int *__restrict__ ci;
     const M *__restrict__ va;
     const V *__restrict__ yg;
@@ -192,13 +291,17 @@ template <class M, class V, bool FOLD, bool KEEP> struct ColOp {
     V *__restrict__ zint;
     V *__restrict__ dx;
     V sigma, hx0, hx1;
-    __device__ __forceinline__ Sum prod(int p) const { return (Sum)va[p] * (Sum)yg[ci[p]]; }
-    __device__ __forceinline__ void epilogue(int j, Sum g, int, double *) const {
-        const V x = hx0 * x0[j] + hx1 * xhat[j];
-        V gs = (V)g - cd[j];
-        if (FOLD) gs = sc[j] * gs;
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return (Sum)r.a * (Sum)yg[r.j]; }
+    __device__ __forceinline__ Pre load(int j) const {
+        return Pre{xhat[j], x0[j], cd[j], ld[j], ud[j], FOLD ? sc[j] : (V)1};
+    }
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &p, int, double *) const {
+        const V x = hx0 * p.x0 + hx1 * p.xh;
+        V gs = (V)g - p.cd;
+        if (FOLD) gs = p.sc * gs;
         const V v = x + sigma * gs;
-        const V xb = clampv(v, ld[j], ud[j]);
+        const V xb = clampv(v, p.ld, p.ud);
         const V xr = (V)2 * xb - x;
         xhat[j] = xr;
         if (KEEP) {
@@ -215,8 +318,12 @@ template <class M, class V, bool FOLD, bool KEEP> struct ColOp {
 //   keep:  y_bar, dy = y - y_hat
 template <class M, class V, bool FOLD, bool KEEP> struct RowOp {
     using Sum = typename AccT<M, V>::type;
+    using Raw = RawT<M>;
     static constexpr int NQ = 0;
-    int tile_nnz;
+    static constexpr bool PREFETCH = true;
+    struct Pre {
+        V y, y0, bd, sr;
+    };
     const int *__restrict__ ci;
     const M *__restrict__ va;
     const V *__restrict__ xg;
@@ -228,18 +335,21 @@ template <class M, class V, bool FOLD, bool KEEP> struct RowOp {
     V *__restrict__ dy;
     V lam_sigma, hy0, hy1;
     long long m1;
-    __device__ __forceinline__ Sum prod(int p) const { return (Sum)va[p] * (Sum)xg[ci[p]]; }
-    __device__ __forceinline__ void epilogue(int i, Sum s, int, double *) const {
-        const V yv = y[i];
-        V r = bd[i] - (V)s;
-        if (FOLD) r = sr[i] * r;
-        V yb = yv + r / lam_sigma;
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return (Sum)r.a * (Sum)xg[r.j]; }
+    __device__ __forceinline__ Pre load(int i) const {
+        return Pre{y[i], y0[i], bd[i], FOLD ? sr[i] : (V)1};
+    }
+    __device__ __forceinline__ void apply(int i, Sum s, const Pre &p, int, double *) const {
+        V r = p.bd - (V)s;
+        if (FOLD) r = p.sr * r;
+        V yb = p.y + r / lam_sigma;
         if (i >= m1) yb = vmax(yb, (V)0);
-        const V yr = (V)2 * yb - yv;
-        y[i] = hy0 * y0[i] + hy1 * yr;
+        const V yr = (V)2 * yb - p.y;
+        y[i] = hy0 * p.y0 + hy1 * yr;
         if (KEEP) {
             ybar[i] = yb;
-            dy[i] = yv - yr;
+            dy[i] = p.y - yr;
         }
     }
 };
@@ -250,8 +360,10 @@ template <class M, class V, bool FOLD, bool KEEP> struct RowOp {
 //   q4 = <dy, A~ dx>                           q5 = ||y_bar - y0||^2 (scaled)
 template <class M, class V> struct CheckRowOp {
     using Sum = D2;
+    using Raw = RawT<M>;
+    using Pre = NoPre;
     static constexpr int NQ = kNQ;
-    int tile_nnz;
+    static constexpr bool PREFETCH = false;
     const int *__restrict__ ci;
     const M *__restrict__ va;
     const V *__restrict__ xbar;
@@ -264,12 +376,13 @@ template <class M, class V> struct CheckRowOp {
     const double *__restrict__ rs;
     const double *__restrict__ ys;
     long long m1;
-    __device__ __forceinline__ Sum prod(int p) const {
-        const double a = (double)va[p];
-        const int j = ci[p];
-        return D2{a * (double)xbar[j], a * (double)dxv[j]};
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const {
+        const double a = (double)r.a;
+        return D2{a * (double)xbar[r.j], a * (double)dxv[r.j]};
     }
-    __device__ __forceinline__ void epilogue(int i, Sum s, int, double *q) const {
+    __device__ __forceinline__ Pre load(int) const { return Pre{}; }
+    __device__ __forceinline__ void apply(int i, Sum s, const Pre &, int, double *q) const {
         const double e = bd[i] - s.a;
         double eo = ro[i] * e, es = rs[i] * e;
         if (i >= m1) {
@@ -295,8 +408,10 @@ template <class M, class V> struct CheckRowOp {
 //   q4 = ||dx||^2 (scaled)                q5 = ||x_bar - x0||^2 (scaled)
 template <class M, class V, bool FOLD> struct CheckColOp {
     using Sum = double;
+    using Raw = RawT<M>;
+    using Pre = NoPre;
     static constexpr int NQ = kNQ;
-    int tile_nnz;
+    static constexpr bool PREFETCH = false;
     const int *__restrict__ ci;
     const M *__restrict__ va;
     const V *__restrict__ ybar;
@@ -311,10 +426,12 @@ template <class M, class V, bool FOLD> struct CheckColOp {
     const double *__restrict__ xs;
     const double *__restrict__ lo;
     const double *__restrict__ uo;
-    __device__ __forceinline__ Sum prod(int p) const {
-        return (double)va[p] * (double)ybar[ci[p]];
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const {
+        return (double)r.a * (double)ybar[r.j];
     }
-    __device__ __forceinline__ void epilogue(int j, Sum g, int, double *q) const {
+    __device__ __forceinline__ Pre load(int) const { return Pre{}; }
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &, int, double *q) const {
         const double xb = (double)xbar[j];
         const double zi = (double)zint[j];
         double e = cd[j] - g;
@@ -340,16 +457,20 @@ template <class M, class V, bool FOLD> struct CheckColOp {
 // are gathered carry the diagonal factors: vg = D_r v, w = D_c A~^T v.
 template <class M, bool FOLD> struct PowColOp {
     using Sum = double;
+    using Raw = RawT<M>;
+    using Pre = NoPre;
     static constexpr int NQ = 1;
-    int tile_nnz;
+    static constexpr bool PREFETCH = false;
     const int *__restrict__ ci;
     const M *__restrict__ va;
     const double *__restrict__ vg;
     const double *__restrict__ inv_norm;
     double *__restrict__ w;
     const double *__restrict__ sc;
-    __device__ __forceinline__ Sum prod(int p) const { return (double)va[p] * vg[ci[p]]; }
-    __device__ __forceinline__ void epilogue(int j, Sum g, int, double *q) const {
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return (double)r.a * vg[r.j]; }
+    __device__ __forceinline__ Pre load(int) const { return Pre{}; }
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &, int, double *q) const {
         const double gn = g * (*inv_norm);
         const double t = FOLD ? sc[j] * gn : gn;
         w[j] = t;
@@ -359,32 +480,36 @@ template <class M, bool FOLD> struct PowColOp {
 
 template <class M, bool FOLD> struct PowRowOp {
     using Sum = double;
+    using Raw = RawT<M>;
+    using Pre = NoPre;
     static constexpr int NQ = 1;
-    int tile_nnz;
+    static constexpr bool PREFETCH = false;
     const int *__restrict__ ci;
     const M *__restrict__ va;
     const double *__restrict__ w;
     double *__restrict__ vg;
     const double *__restrict__ sr;
-    __device__ __forceinline__ Sum prod(int p) const { return (double)va[p] * w[ci[p]]; }
-    __device__ __forceinline__ void epilogue(int i, Sum s, int, double *q) const {
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return (double)r.a * w[r.j]; }
+    __device__ __forceinline__ Pre load(int) const { return Pre{}; }
+    __device__ __forceinline__ void apply(int i, Sum s, const Pre &, int, double *q) const {
         const double t = FOLD ? sr[i] * s : s;
         vg[i] = t;
         q[0] += t * s;  // ||A~ A~^T v||^2
     }
 };
 
-__global__ __launch_bounds__(kWG) void k_power_reduce(const double *__restrict__ pc, int nc,
-                                                      const double *__restrict__ pr, int nr,
-                                                      double *__restrict__ hist,
-                                                      double *__restrict__ inv_norm) {
-    __shared__ double red[4];
+__global__ __launch_bounds__(kRedWG) void k_power_reduce(const double *__restrict__ pc, int nc,
+                                                         const double *__restrict__ pr, int nr,
+                                                         double *__restrict__ hist,
+                                                         double *__restrict__ inv_norm) {
+    __shared__ double red[kRedWG / 64];
     double s = 0.0;
-    for (int k = threadIdx.x; k < nc; k += kWG) s += pc[k];
-    s = block_sum(s, red);
+    for (int k = threadIdx.x; k < nc; k += kRedWG) s += pc[k];
+    s = block_sum_1024(s, red);
     double t = 0.0;
-    for (int k = threadIdx.x; k < nr; k += kWG) t += pr[k];
-    t = block_sum(t, red);
+    for (int k = threadIdx.x; k < nr; k += kRedWG) t += pr[k];
+    t = block_sum_1024(t, red);
     if (threadIdx.x == 0) {
         *hist = s;
         *inv_norm = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
@@ -394,13 +519,18 @@ __global__ __launch_bounds__(kWG) void k_power_reduce(const double *__restrict__
 // ------------------------------------------------------------------------- launch helpers
 
 template <class Op>
-hipError_t run_pass(const DevMat &M, Op op, double *parts, hipStream_t st) {
+hipError_t run_pass(const DevMat &M, Op op, double *parts, hipStream_t st,
+                    hipEvent_t ev_mid = nullptr) {
     using S = typename Op::Sum;
-    op.tile_nnz = M.tile_nnz;
-    const size_t lds = (size_t)(M.tile_nnz + M.tile_rows) * sizeof(S);
+    // LDS: staged products (tile_nnz), row sums (tile_rows), row pointers (tile_rows + 1)
+    const size_t lds = (size_t)(M.tile_nnz + M.tile_rows) * sizeof(S) + (M.tile_rows + 1) * sizeof(int);
     if (M.n_items > 0)
         hipLaunchKernelGGL(k_pass<Op>, dim3(M.n_items), dim3(kWG), lds, st, M.items, M.rp, op,
-                           reinterpret_cast<S *>(M.split_part), parts);
+                           reinterpret_cast<S *>(M.split_part), parts, M.tile_nnz, M.tile_rows);
+    if (ev_mid) {
+        hipError_t e = hipEventRecord(ev_mid, st);
+        if (e != hipSuccess) return e;
+    }
     if (M.n_split > 0)
         hipLaunchKernelGGL(k_split<Op>, dim3(M.n_split), dim3(64), 0, st, M.splits,
                            reinterpret_cast<const S *>(M.split_part), op, parts, M.n_items);
@@ -408,7 +538,8 @@ hipError_t run_pass(const DevMat &M, Op op, double *parts, hipStream_t st) {
 }
 
 template <class M, class V, bool FOLD, bool KEEP>
-hipError_t col_pass(const DevMat &T, const VecSet<V> &v, const IterScalars &s, hipStream_t st) {
+hipError_t col_pass(const DevMat &T, const VecSet<V> &v, const IterScalars &s, hipStream_t st,
+                    hipEvent_t ev) {
     ColOp<M, V, FOLD, KEEP> op;
     op.ci = T.ci;
     op.va = reinterpret_cast<const M *>(T.va);
@@ -416,11 +547,12 @@ hipError_t col_pass(const DevMat &T, const VecSet<V> &v, const IterScalars &s, h
     op.xhat = v.xhat; op.x0 = v.x0; op.cd = v.cd; op.ld = v.ld; op.ud = v.ud; op.sc = v.sc;
     op.xbar = v.xbar; op.zint = v.zint; op.dx = v.dx;
     op.sigma = (V)s.sigma; op.hx0 = (V)s.hx0; op.hx1 = (V)s.hx1;
-    return run_pass(T, op, nullptr, st);
+    return run_pass(T, op, nullptr, st, ev);
 }
 
 template <class M, class V, bool FOLD, bool KEEP>
-hipError_t row_pass(const DevMat &A, const VecSet<V> &v, const IterScalars &s, hipStream_t st) {
+hipError_t row_pass(const DevMat &A, const VecSet<V> &v, const IterScalars &s, hipStream_t st,
+                    hipEvent_t ev) {
     RowOp<M, V, FOLD, KEEP> op;
     op.ci = A.ci;
     op.va = reinterpret_cast<const M *>(A.va);
@@ -428,7 +560,7 @@ hipError_t row_pass(const DevMat &A, const VecSet<V> &v, const IterScalars &s, h
     op.y = v.y; op.y0 = v.y0; op.bd = v.bd; op.sr = v.sr; op.ybar = v.ybar; op.dy = v.dy;
     op.lam_sigma = (V)s.lam_sigma; op.hy0 = (V)s.hy0; op.hy1 = (V)s.hy1;
     op.m1 = s.m1;
-    return run_pass(A, op, nullptr, st);
+    return run_pass(A, op, nullptr, st, ev);
 }
 
 template <class M, class V>
@@ -441,7 +573,7 @@ hipError_t check_row(const DevMat &A, const VecSet<V> &v, const CheckData &cd, c
     op.bd = bd; op.ro = cd.ro; op.rs = cd.rs; op.ys = cd.ys; op.m1 = m1;
     hipError_t e = run_pass(A, op, parts, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, parts, A.n_items + A.n_split, kNQ,
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedWG), 0, st, parts, A.n_items + A.n_split, kNQ,
                        out);
     return hipGetLastError();
 }
@@ -457,7 +589,7 @@ hipError_t check_col(const DevMat &T, const VecSet<V> &v, const CheckData &cd, c
     op.lo = cd.lo; op.uo = cd.uo;
     hipError_t e = run_pass(T, op, parts, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, st, parts, T.n_items + T.n_split, kNQ,
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedWG), 0, st, parts, T.n_items + T.n_split, kNQ,
                        out);
     return hipGetLastError();
 }
@@ -478,7 +610,7 @@ hipError_t power_iter(const DevMat &A, const DevMat &T, double *vg, double *w, c
     orw.w = w; orw.vg = vg; orw.sr = sr;
     e = run_pass(A, orw, pr, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_power_reduce, dim3(1), dim3(kWG), 0, st, pc, T.n_items + T.n_split,
+    hipLaunchKernelGGL(k_power_reduce, dim3(1), dim3(kRedWG), 0, st, pc, T.n_items + T.n_split,
                        pr, A.n_items + A.n_split, hist, inv_norm);
     return hipGetLastError();
 }
@@ -497,18 +629,18 @@ template <class D, class S> __global__ void k_copy(D *dst, const S *src, long lo
 }
 template <class S>
 __global__ void k_scale_out(double *out, const S *v, const double *mul, double smul,
-                            long long n) {
+                            const int *perm, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
-        out[i] = (mul ? mul[i] : smul) * (double)v[i];
+        out[perm ? perm[i] : i] = (mul ? mul[i] : smul) * (double)v[i];
 }
 template <class S>
 __global__ void k_xcur_out(double *out, const S *x0, const S *xh, double hx0, double hx1,
-                           const double *mul, double smul, long long n) {
+                           const double *mul, double smul, const int *perm, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const S x = (S)hx0 * x0[i] + (S)hx1 * xh[i];
-        out[i] = (mul ? mul[i] : smul) * (double)x;
+        out[perm ? perm[i] : i] = (mul ? mul[i] : smul) * (double)x;
     }
 }
 
@@ -524,37 +656,37 @@ inline dim3 grid_for(long long n) {
 // ------------------------------------------------------------------------- dispatch
 
 hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vs,
-                           const IterScalars &s, hipStream_t st) {
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev) {
     if (prec == 0) {
         auto &v = *static_cast<const VecSet<double> *>(vs);
-        return keep ? col_pass<double, double, false, true>(T, v, s, st)
-                    : col_pass<double, double, false, false>(T, v, s, st);
+        return keep ? col_pass<double, double, false, true>(T, v, s, st, ev)
+                    : col_pass<double, double, false, false>(T, v, s, st, ev);
     }
     if (prec == 1) {
         auto &v = *static_cast<const VecSet<float> *>(vs);
-        return keep ? col_pass<float, float, true, true>(T, v, s, st)
-                    : col_pass<float, float, true, false>(T, v, s, st);
+        return keep ? col_pass<float, float, true, true>(T, v, s, st, ev)
+                    : col_pass<float, float, true, false>(T, v, s, st, ev);
     }
     auto &v = *static_cast<const VecSet<double> *>(vs);
-    return keep ? col_pass<float, double, true, true>(T, v, s, st)
-                : col_pass<float, double, true, false>(T, v, s, st);
+    return keep ? col_pass<float, double, true, true>(T, v, s, st, ev)
+                : col_pass<float, double, true, false>(T, v, s, st, ev);
 }
 
 hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vs,
-                           const IterScalars &s, hipStream_t st) {
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev) {
     if (prec == 0) {
         auto &v = *static_cast<const VecSet<double> *>(vs);
-        return keep ? row_pass<double, double, false, true>(A, v, s, st)
-                    : row_pass<double, double, false, false>(A, v, s, st);
+        return keep ? row_pass<double, double, false, true>(A, v, s, st, ev)
+                    : row_pass<double, double, false, false>(A, v, s, st, ev);
     }
     if (prec == 1) {
         auto &v = *static_cast<const VecSet<float> *>(vs);
-        return keep ? row_pass<float, float, true, true>(A, v, s, st)
-                    : row_pass<float, float, true, false>(A, v, s, st);
+        return keep ? row_pass<float, float, true, true>(A, v, s, st, ev)
+                    : row_pass<float, float, true, false>(A, v, s, st, ev);
     }
     auto &v = *static_cast<const VecSet<double> *>(vs);
-    return keep ? row_pass<float, double, true, true>(A, v, s, st)
-                : row_pass<float, double, true, false>(A, v, s, st);
+    return keep ? row_pass<float, double, true, true>(A, v, s, st, ev)
+                : row_pass<float, double, true, false>(A, v, s, st, ev);
 }
 
 hipError_t launch_check_row(int prec, const DevMat &A, const void *vs, const CheckData &cd,
@@ -621,28 +753,28 @@ hipError_t launch_f2d(double *dst, const float *src, long long n, hipStream_t st
     return hipGetLastError();
 }
 hipError_t launch_scale_out(double *out, const void *v, bool v_f32, const double *mul,
-                            double smul, long long n, hipStream_t st) {
+                            double smul, const int *perm, long long n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (v_f32)
         hipLaunchKernelGGL(k_scale_out<float>, grid_for(n), dim3(256), 0, st, out,
-                           static_cast<const float *>(v), mul, smul, n);
+                           static_cast<const float *>(v), mul, smul, perm, n);
     else
         hipLaunchKernelGGL(k_scale_out<double>, grid_for(n), dim3(256), 0, st, out,
-                           static_cast<const double *>(v), mul, smul, n);
+                           static_cast<const double *>(v), mul, smul, perm, n);
     return hipGetLastError();
 }
 hipError_t launch_xcur_out(double *out, const void *x0, const void *xhat, bool v_f32,
-                           double hx0, double hx1, const double *mul, double smul, long long n,
-                           hipStream_t st) {
+                           double hx0, double hx1, const double *mul, double smul,
+                           const int *perm, long long n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (v_f32)
         hipLaunchKernelGGL(k_xcur_out<float>, grid_for(n), dim3(256), 0, st, out,
                            static_cast<const float *>(x0), static_cast<const float *>(xhat),
-                           hx0, hx1, mul, smul, n);
+                           hx0, hx1, mul, smul, perm, n);
     else
         hipLaunchKernelGGL(k_xcur_out<double>, grid_for(n), dim3(256), 0, st, out,
                            static_cast<const double *>(x0), static_cast<const double *>(xhat),
-                           hx0, hx1, mul, smul, n);
+                           hx0, hx1, mul, smul, perm, n);
     return hipGetLastError();
 }
 

@@ -89,7 +89,8 @@ int validate_options(const hprlp_options &o, std::string &err) {
               o.alpha1 < 1 && o.alpha2 > 0 && o.alpha2 < 1 && o.alpha3 > 0 && o.alpha3 < 1 &&
               o.sigma0 > 0 && o.ruiz_iters >= 0 && o.power_max_iter >= 1 && o.power_tol >= 0 &&
               (o.precision == HPRLP_FP64 || o.precision == HPRLP_MIXED) && o.tol_switch > 0 &&
-              o.tile_nnz >= 256 && o.tile_rows >= 1 && o.tile_nnz + o.tile_rows <= 4096 &&
+              o.tile_nnz >= 256 && o.tile_nnz <= kMaxTileNnz && o.tile_rows >= 1 &&
+              o.tile_rows <= kMaxTileRows &&
               o.short_max >= 1 && o.short_max <= o.tile_nnz &&
               o.split_len >= o.short_max && o.chunk_nnz >= 256;
     if (!ok) err = "invalid option value";
@@ -98,7 +99,7 @@ int validate_options(const hprlp_options &o, std::string &err) {
 
 void resolve_options(hprlp_options &o) {
     if (o.tile_nnz <= 0) o.tile_nnz = 2048;
-    if (o.tile_rows <= 0) o.tile_rows = 1024;
+    if (o.tile_rows <= 0) o.tile_rows = 512;
     if (o.short_max <= 0) o.short_max = 256;
     if (o.split_len <= 0) o.split_len = 8192;
     if (o.chunk_nnz <= 0) o.chunk_nnz = 4096;
@@ -179,7 +180,11 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
     auto inst = [&](int64_t r) { return inst_of_row ? inst_of_row[r] : 0; };
     int64_t r0 = 0, tnnz = 0;
     auto close_tile = [&](int64_t r1) {
-        if (r1 > r0) tiles.push_back(make_int4((int)r0, (int)r1, inst(r0), IT_TILE));
+        if (r1 > r0) {
+            const int nrows = (int)(r1 - r0), cnt = (int)(rowptr[r1] - rowptr[r0]);
+            tiles.push_back(make_int4((int)r0, (int)rowptr[r0], inst(r0),
+                                      (nrows << 14) | (cnt << 2) | IT_TILE));
+        }
         r0 = r1;
         tnnz = 0;
     };
@@ -211,12 +216,29 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
                      [](const std::pair<int64_t, int64_t> &a,
                         const std::pair<int64_t, int64_t> &b) { return a.first > b.first; });
     for (auto &lr : longlen)
-        longrows.push_back(make_int4((int)lr.second, inst(lr.second), 0, IT_ROW));
-    // heaviest work first so the tail of the launch is made of small tiles
-    out.items.reserve(chunks.size() + longrows.size() + tiles.size());
-    out.items.insert(out.items.end(), chunks.begin(), chunks.end());
-    out.items.insert(out.items.end(), longrows.begin(), longrows.end());
-    out.items.insert(out.items.end(), tiles.begin(), tiles.end());
+        longrows.push_back(make_int4((int)lr.second, (int)rowptr[lr.second],
+                                     (int)rowptr[lr.second + 1], (inst(lr.second) << 2) | IT_ROW));
+    // Heaviest work first so the tail of the launch is made of small tiles.  Each class is
+    // padded to a multiple of kXCD and interleaved: workgroup b runs on XCD b % kXCD, so the
+    // item at position kXCD*k + x of a class segment is item x*q + k of the class (q = padded
+    // length / kXCD): XCD x walks the contiguous range [x*q, (x+1)*q).
+    auto append = [&](std::vector<int4> &cls) {
+        if (cls.empty()) return;
+        while (cls.size() % kXCD) cls.push_back(make_int4(0, 0, 0, IT_EMPTY));
+        const size_t q = cls.size() / kXCD;
+        for (size_t k = 0; k < q; ++k)
+            for (int x = 0; x < kXCD; ++x) out.items.push_back(cls[x * q + k]);
+    };
+    // Whole-workgroup rows are sorted by decreasing length: contiguous ranges would give the
+    // first XCD all the heavy rows, so they are only range-interleaved when their lengths
+    // are uniform (e.g. the demand rows of a transportation LP); otherwise the plain
+    // round-robin deal keeps every XCD's share of heavy and light rows equal.
+    const bool uniform_long = longlen.empty() || longlen.front().first <= longlen.back().first + longlen.back().first / 4;
+    out.items.reserve(chunks.size() + longrows.size() + tiles.size() + 3 * kXCD);
+    append(chunks);
+    if (uniform_long) append(longrows);
+    else out.items.insert(out.items.end(), longrows.begin(), longrows.end());
+    append(tiles);
     out.n_tiles = (long long)tiles.size();
     out.n_rowitems = (long long)longrows.size();
     out.n_chunks = (long long)chunks.size();

@@ -39,7 +39,8 @@ class Options(C.Structure):
                 ("use_halpern", C.c_int), ("use_restart", C.c_int), ("sigma_update", C.c_int),
                 ("precision", C.c_int), ("tol_switch", C.c_double), ("tile_nnz", C.c_int),
                 ("tile_rows", C.c_int), ("short_max", C.c_int), ("split_len", C.c_int),
-                ("chunk_nnz", C.c_int), ("profile", C.c_int), ("verbose", C.c_int)]
+                ("chunk_nnz", C.c_int), ("reorder", C.c_int), ("profile", C.c_int),
+                ("verbose", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -51,7 +52,8 @@ class Stats(C.Structure):
                 ("t_power_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("bytes_per_iter", C.c_double), ("col_pass_ms", C.c_double),
                 ("row_pass_ms", C.c_double), ("col_pass_launches", C.c_longlong),
-                ("row_pass_launches", C.c_longlong), ("n_checks", C.c_longlong)]
+                ("row_pass_launches", C.c_longlong), ("split_ms", C.c_double),
+                ("n_checks", C.c_longlong)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
