@@ -75,9 +75,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
-    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "fp64a32"])
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--time-limit", type=float, default=100.0, help="seconds per solve")
+    ap.add_argument("--time-limit", type=float, default=60.0, help="seconds per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time pass launches with HIP events (default: every 50th "
@@ -102,7 +102,7 @@ def main():
     print(f"[bench] {args.config}: m={lp.m} n={lp.n} nnz={lp.nnz} generated in {t_gen:.1f}s",
           file=sys.stderr, flush=True)
     opts = dict(tol=args.tol, time_limit=args.time_limit,
-                precision=hprlp.MIXED if prec == "mixed" else hprlp.FP64,
+                precision={"mixed": hprlp.MIXED, "fp64a32": hprlp.FP64_A32}.get(prec, hprlp.FP64),
                 profile=0 if args.no_profile else 50)
     t0 = time.perf_counter()
     solver = hprlp.Solver(lp, **opts)
@@ -130,7 +130,7 @@ def main():
     value = float(np.mean(times))
     solved = all(s["status"] == "OPTIMAL" for s in stats)
     iters = int(st["iters"])
-    s_val = 4 if prec == "mixed" else 8
+    s_val = 4 if prec in ("mixed", "fp64a32") else 8
     s_vec = 4 if (prec == "mixed" and st["iters_fp32"] == iters) else 8
     col_b, row_b = pass_bytes(lp.m, lp.n, lp.nnz, s_val, s_vec)
     out = {

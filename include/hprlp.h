@@ -47,7 +47,7 @@ typedef enum {
     HPRLP_EDIM = -2,         /* bad sizes, rowptr not monotone, column index out of range */
     HPRLP_ENONFINITE = -3,   /* NaN anywhere, or an infinite value in A, b or c           */
     HPRLP_EBOUNDS = -4,      /* l_j > u_j, l_j = +inf or u_j = -inf                       */
-    HPRLP_ENOTLOSSLESS = -5, /* MIXED precision asked but some A value is not FP32-exact  */
+    HPRLP_ENOTLOSSLESS = -5, /* FP32 storage of A asked but some A value is not FP32-exact */
     HPRLP_ENOMEM = -6,       /* host allocation failed                                    */
     HPRLP_EHIP = -7,         /* a HIP runtime call failed                                 */
     HPRLP_ESTATE = -8        /* call not valid in the handle's current state              */
@@ -61,7 +61,12 @@ typedef enum {
     HPRLP_NUMERICAL = 4   /* a NaN appeared in the check quantities                     */
 } hprlp_status;
 
-typedef enum { HPRLP_FP64 = 0, HPRLP_MIXED = 1 } hprlp_precision;
+/* FP64: A~ stored in FP64, FP64 vectors (the plain solver).
+ * MIXED: A stored in FP32 (must be exact), FP32 vectors until the relative KKT residual
+ *   reaches tol_switch, then FP64 vectors; checks, restart merit and sigma always in FP64.
+ * FP64_A32: A stored in FP32 (must be exact), FP64 vectors throughout: FP64 results with
+ *   8 instead of 12 bytes per nonzero (FP32 x FP64 products are exact in FP64). */
+typedef enum { HPRLP_FP64 = 0, HPRLP_MIXED = 1, HPRLP_FP64_A32 = 2 } hprlp_precision;
 
 typedef struct {
     double tol;              /* termination tolerance (default 1e-8; Section 4.1)          */
@@ -79,8 +84,10 @@ typedef struct {
     int use_halpern;         /* 1: Halpern averaging (Algorithm 2); 0: plain PR iteration  */
     int use_restart;         /* 1: restart criteria of Section 3.1                         */
     int sigma_update;        /* 1: SigmaUpdate (Algorithm 3); 0: sigma stays sigma0        */
-    int precision;           /* HPRLP_FP64 or HPRLP_MIXED (FP32 until tol_switch)          */
+    int precision;           /* hprlp_precision (default HPRLP_FP64)                       */
     double tol_switch;       /* MIXED: switch to FP64 once rel. KKT <= this (default 1e-5) */
+    int stall_checks;        /* MIXED: also switch when the best rel. KKT of the FP32 phase */
+                             /* has not halved over this many checks (default 10; 0: off)  */
     int tile_nnz;            /* schedule: nonzeros staged per tile (0 = default)           */
     int tile_rows;           /* schedule: rows per tile (0 = default)                      */
     int short_max;           /* schedule: longest row kept in tiles (0 = default)          */

@@ -3,8 +3,8 @@
 The solver lives in ``libhprlp.so`` (C ABI in ``include/hprlp.h``); ``hprlp`` is its thin
 Python binding.
 """
-from .hprlp import (FP64, MIXED, HPRLPError, Solution, Solver, default_options, load,
+from .hprlp import (FP64, FP64_A32, MIXED, HPRLPError, Solution, Solver, default_options, load,
                     workspace_bytes)
 
-__all__ = ["FP64", "MIXED", "HPRLPError", "Solution", "Solver", "default_options", "load",
+__all__ = ["FP64", "FP64_A32", "MIXED", "HPRLPError", "Solution", "Solver", "default_options", "load",
            "workspace_bytes"]

@@ -54,7 +54,8 @@ struct Carver {
 struct hprlp_handle {
     hprlp_options opt{};
     int64_t m1 = 0, m2 = 0, m = 0, n = 0, nnz = 0;
-    bool mixed = false;
+    bool mixed = false;   // A stored in FP32 (original values) with the scaling folded
+    bool f32phase = false;  // MIXED: starts with FP32 vectors
     hipStream_t st = nullptr;
     DevMat A, T;
     VecSet<double> v64;
@@ -99,7 +100,7 @@ int fail(hprlp_handle *h, int code, const std::string &msg) {
 // Device memory plan; the same function sizes the workspace (dry run) and carves it.
 struct Plan {
     int64_t m, n, nnz;
-    bool mixed;
+    bool mixed, f32phase;
     int itemsA, itemsT, splitA, splitT, slotsA, slotsT;
     int power_cap;
 };
@@ -130,6 +131,8 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     if (p.mixed) {
         d.sc = cv.arr<double>(n);
         d.sr = cv.arr<double>(m);
+    }
+    if (p.f32phase) {
         f.xhat = cv.arr<float>(n); f.x0 = cv.arr<float>(n); f.cd = cv.arr<float>(n);
         f.ld = cv.arr<float>(n); f.ud = cv.arr<float>(n); f.sc = cv.arr<float>(n);
         f.xbar = cv.arr<float>(n); f.zint = cv.arr<float>(n); f.dx = cv.arr<float>(n);
@@ -173,11 +176,13 @@ size_t plan_bytes(const Plan &p) {
 // long rows plus split rows are at most `rows`; chunks at most nnz/chunk + split rows.
 Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o) {
     Plan p;
-    p.m = m; p.n = n; p.nnz = nnz; p.mixed = o.precision == HPRLP_MIXED;
+    p.m = m; p.n = n; p.nnz = nnz; p.mixed = o.precision != HPRLP_FP64;
+    p.f32phase = o.precision == HPRLP_MIXED;
     const int64_t ch = nnz / o.chunk_nnz + 1;
-    // + 3 * kXCD padding items (one partial class of each kind)
-    p.itemsA = (int)std::min<int64_t>(2 * m + ch + 3 * kXCD, INT32_MAX / 8);
-    p.itemsT = (int)std::min<int64_t>(2 * n + ch + 3 * kXCD, INT32_MAX / 8);
+    // padding items: at most kXCD-1 per class segment (chunks, tiles, and each equal-length
+    // run of whole-workgroup rows, which has >= 16*kXCD rows): bounded by kXCD + rows/16
+    p.itemsA = (int)std::min<int64_t>(2 * m + ch + 3 * kXCD + m / 16, INT32_MAX / 8);
+    p.itemsT = (int)std::min<int64_t>(2 * n + ch + 3 * kXCD + n / 16, INT32_MAX / 8);
     p.splitA = (int)std::min<int64_t>(m, nnz / o.split_len + 1);
     p.splitT = (int)std::min<int64_t>(n, nnz / o.split_len + 1);
     p.slotsA = (int)ch + p.splitA;
@@ -309,6 +314,8 @@ int create_device(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
             for (int64_t j = 0; j < n; ++j) sc2[j] = sc.dc[j] * sc.dc[j];
             for (int64_t i = 0; i < m; ++i) sr2[i] = sc.dr[i] * sc.dr[i];
             if ((rc = up(h->v64.sc, sc2)) || (rc = up(h->v64.sr, sr2))) return rc;
+        }
+        if (h->f32phase) {
             auto upf = [&](float *dst, const std::vector<double> &v) {
                 std::vector<float> f(v.size());
                 for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
@@ -355,6 +362,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->sigma_update = 1;
     o->precision = HPRLP_FP64;
     o->tol_switch = 1e-5;
+    o->stall_checks = 10;
     o->reorder = 1;
     o->profile = 0;
     o->verbose = 0;
@@ -400,7 +408,8 @@ extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t 
     hprlp_handle *h = new (std::nothrow) hprlp_handle();
     if (!h) return fail(nullptr, HPRLP_ENOMEM, "handle allocation failed");
     h->opt = o; h->m1 = m1; h->m2 = m2; h->m = m; h->n = n; h->nnz = nnz;
-    h->mixed = o.precision == HPRLP_MIXED;
+    h->mixed = o.precision != HPRLP_FP64;
+    h->f32phase = o.precision == HPRLP_MIXED;
     h->st = static_cast<hipStream_t>(stream);
 
     // ---- host preprocessing
@@ -696,7 +705,7 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     const double t_start = now_ms();
     h->trace.clear();
     h->stats = hprlp_stats_t{};
-    h->prec = h->mixed ? 1 : 0;
+    h->prec = h->f32phase ? 1 : (h->mixed ? 2 : 0);
     h->t = h->k = h->r = 0;
     h->sigma = o.sigma0;
     int rc;
@@ -735,6 +744,7 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
 
     double merit0 = 0, merit_prev = 0;
     bool pending_first = false;
+    std::vector<double> kkt_hist;  // MIXED: rel. KKT at the checks of the FP32 phase
     int st_out = HPRLP_UNSOLVED;
     long long iters_fp32 = 0;
     const long long ce = o.check_every;
@@ -831,8 +841,20 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
             merit_prev = merit;
         }
         h->trace.push_back(row);
-        if (h->prec == 1 && kkt <= o.tol_switch)
-            if ((rc = promote(h))) return rc;
+        if (h->prec == 1) {
+            // switch to FP64 at tol_switch, or when FP32 rounding stalls the iteration: the
+            // best residual of the last stall_checks checks is not below half of the best
+            // one before them
+            bool sw = kkt <= o.tol_switch;
+            kkt_hist.push_back(kkt);
+            const size_t S = (size_t)o.stall_checks, H = kkt_hist.size();
+            if (!sw && S > 0 && H > S) {
+                const double before = *std::min_element(kkt_hist.begin(), kkt_hist.end() - S);
+                const double recent = *std::min_element(kkt_hist.end() - S, kkt_hist.end());
+                sw = recent > 0.5 * before;
+            }
+            if (sw && (rc = promote(h))) return rc;
+        }
     }
     HIPCHK(h, hipStreamSynchronize(h->st));
     if (pp && (rc = flush_prof())) return rc;
@@ -855,7 +877,7 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     hprlp_stats_t &s = h->stats;
     s.iters = h->k;
     s.restarts = h->r;
-    s.iters_fp32 = h->mixed ? iters_fp32 : 0;
+    s.iters_fp32 = h->f32phase ? iters_fp32 : 0;
     s.status = st_out;
     s.power_iters = piters;
     s.sigma = h->sigma;

@@ -75,10 +75,10 @@ int validate_problem(int64_t m1, int64_t m2, int64_t n, const int64_t *rowptr,
             return HPRLP_EBOUNDS;
         }
     }
-    if (o.precision == HPRLP_MIXED)
+    if (o.precision != HPRLP_FP64)
         for (int64_t p = 0; p < nnz; ++p)
             if ((double)(float)val[p] != val[p]) {
-                err = "MIXED precision needs every A value exactly representable in FP32";
+                err = "FP32 storage of A needs every A value exactly representable in FP32";
                 return HPRLP_ENOTLOSSLESS;
             }
     return HPRLP_OK;
@@ -88,7 +88,8 @@ int validate_options(const hprlp_options &o, std::string &err) {
     bool ok = o.tol > 0 && o.check_every >= 1 && o.max_iter >= 1 && o.alpha1 > 0 &&
               o.alpha1 < 1 && o.alpha2 > 0 && o.alpha2 < 1 && o.alpha3 > 0 && o.alpha3 < 1 &&
               o.sigma0 > 0 && o.ruiz_iters >= 0 && o.power_max_iter >= 1 && o.power_tol >= 0 &&
-              (o.precision == HPRLP_FP64 || o.precision == HPRLP_MIXED) && o.tol_switch > 0 &&
+              (o.precision == HPRLP_FP64 || o.precision == HPRLP_MIXED ||
+               o.precision == HPRLP_FP64_A32) && o.tol_switch > 0 &&
               o.tile_nnz >= 256 && o.tile_nnz <= kMaxTileNnz && o.tile_rows >= 1 &&
               o.tile_rows <= kMaxTileRows &&
               o.short_max >= 1 && o.short_max <= o.tile_nnz &&
@@ -229,15 +230,20 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
         for (size_t k = 0; k < q; ++k)
             for (int x = 0; x < kXCD; ++x) out.items.push_back(cls[x * q + k]);
     };
-    // Whole-workgroup rows are sorted by decreasing length: contiguous ranges would give the
-    // first XCD all the heavy rows, so they are only range-interleaved when their lengths
-    // are uniform (e.g. the demand rows of a transportation LP); otherwise the plain
-    // round-robin deal keeps every XCD's share of heavy and light rows equal.
-    const bool uniform_long = longlen.empty() || longlen.front().first <= longlen.back().first + longlen.back().first / 4;
-    out.items.reserve(chunks.size() + longrows.size() + tiles.size() + 3 * kXCD);
+    // Whole-workgroup rows are sorted by decreasing length: contiguous ranges of a mixed-length
+    // list would give the first XCD all the heavy rows.  Runs of equal length that fill every
+    // XCD many times over (e.g. the supply and the demand rows of a transportation LP) are
+    // range-interleaved; the rest is dealt round-robin, which keeps the XCD shares equal.
+    out.items.reserve(chunks.size() + longrows.size() + tiles.size() + 4 * kXCD + longlen.size());
     append(chunks);
-    if (uniform_long) append(longrows);
-    else out.items.insert(out.items.end(), longrows.begin(), longrows.end());
+    for (size_t a = 0; a < longrows.size();) {
+        size_t e = a;
+        while (e < longrows.size() && longlen[e].first == longlen[a].first) ++e;
+        std::vector<int4> run(longrows.begin() + a, longrows.begin() + e);
+        if (run.size() >= (size_t)(16 * kXCD)) append(run);
+        else out.items.insert(out.items.end(), run.begin(), run.end());
+        a = e;
+    }
     append(tiles);
     out.n_tiles = (long long)tiles.size();
     out.n_rowitems = (long long)longrows.size();

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libhprlp.so")
 OK, EINVAL, EDIM, ENONFINITE, EBOUNDS, ENOTLOSSLESS, ENOMEM, EHIP, ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 STATUS = {0: "UNSOLVED", 1: "OPTIMAL", 2: "ITER_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL"}
-FP64, MIXED = 0, 1
+FP64, MIXED, FP64_A32 = 0, 1, 2
 XBAR, YBAR, ZBAR, XCUR, YCUR, DROW, DCOL = range(7)
 TRACE_COLS = ["k", "t", "r", "sigma", "merit", "merit0", "merit_prev", "rel_p", "rel_d",
               "rel_gap", "pobj", "dobj", "dx", "dy", "err_p", "err_d", "restart",
@@ -37,7 +37,8 @@ class Options(C.Structure):
                 ("normalize_bc", C.c_int), ("power_max_iter", C.c_int),
                 ("power_tol", C.c_double), ("lambda_override", C.c_double),
                 ("use_halpern", C.c_int), ("use_restart", C.c_int), ("sigma_update", C.c_int),
-                ("precision", C.c_int), ("tol_switch", C.c_double), ("tile_nnz", C.c_int),
+                ("precision", C.c_int), ("tol_switch", C.c_double),
+                ("stall_checks", C.c_int), ("tile_nnz", C.c_int),
                 ("tile_rows", C.c_int), ("short_max", C.c_int), ("split_len", C.c_int),
                 ("chunk_nnz", C.c_int), ("reorder", C.c_int), ("profile", C.c_int),
                 ("verbose", C.c_int)]
