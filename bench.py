@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="zipf1m", choices=["tiny", "zipf1m", "zipf4m", "batch256", "transport10m"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "fp64a32"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--time-limit", type=float, default=60.0, help="seconds per solve")
@@ -95,7 +95,7 @@ def main():
     import lpgen
     from paper_2408_12179_amd import hprlp
 
-    prec = args.precision or {"c2": "mixed", "c4": "mixed"}.get(args.config, "fp64")
+    prec = args.precision or {"zipf4m": "mixed", "transport10m": "mixed"}.get(args.config, "fp64")
     t0 = time.perf_counter()
     lp = lpgen.make(args.config)
     t_gen = time.perf_counter() - t0

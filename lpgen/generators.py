@@ -372,32 +372,32 @@ def tiny_boxed_lp(m1: int, m2: int, n: int, seed: int, density=0.7) -> LP:
 # --------------------------------------------------------------------------------------
 
 WORKLOADS = {
-    "c0": "tiny random sparse LP: m1=50, m2=50, n=200, Bernoulli(0.05), plain FP64",
-    "c1": "single large sparse LP: m=500k (half equality), n=1M, row lengths U{5..40}, "
+    "tiny": "tiny random sparse LP: m1=50, m2=50, n=200, Bernoulli(0.05), plain FP64",
+    "zipf1m": "single large sparse LP: m=500k (half equality), n=1M, row lengths U{5..40}, "
           "Zipf(1.1) columns, plain FP64",
-    "c2": "single larger sparse LP: m=2M, n=4M, same generator as c1, FP32->FP64",
-    "c3": "batched: 256 Bernoulli LPs, m_i~U{1k..50k}, n_i=2m_i, 8-30 nnz/row",
-    "c4": "transportation 2000 x 5000: n=10M, m=7000, FP32->FP64",
+    "zipf4m": "single larger sparse LP: m=2M, n=4M, same generator as zipf1m, FP32->FP64",
+    "batch256": "batched: 256 Bernoulli LPs, m_i~U{1k..50k}, n_i=2m_i, 8-30 nnz/row",
+    "transport10m": "transportation 2000 x 5000: n=10M, m=7000, FP32->FP64",
 }
 
 
 def make(name: str, scale: float = 1.0) -> LP:
     """Build a named workload.  ``scale`` shrinks the large workloads (row and column counts)
     for tests that must finish in seconds; scale=1 gives the full size."""
-    if name == "c0":
-        return bernoulli_lp(50, 50, 200, 0.05, seed=BASE_SEED + 0, name="c0")
-    if name in ("c1", "c2"):
-        m = {"c1": 500_000, "c2": 2_000_000}[name]
+    if name == "tiny":
+        return bernoulli_lp(50, 50, 200, 0.05, seed=BASE_SEED + 0, name="tiny")
+    if name in ("zipf1m", "zipf4m"):
+        m = {"zipf1m": 500_000, "zipf4m": 2_000_000}[name]
         m = max(8, int(round(m * scale)))
-        k = 1 if name == "c1" else 2
+        k = 1 if name == "zipf1m" else 2
         return zipf_lp(m // 2, m - m // 2, 2 * m, seed=BASE_SEED + k, name=name)
-    if name == "c3":
+    if name == "batch256":
         n_inst = max(1, int(round(256 * scale))) if scale < 1 else 256
         mr = (1000, 50000) if scale >= 1 else (max(20, int(1000 * scale)),
                                                 max(40, int(50000 * scale)))
-        return batched_lp(n_inst, m_range=mr, name="c3")
-    if name == "c4":
+        return batched_lp(n_inst, m_range=mr, name="batch256")
+    if name == "transport10m":
         s = max(2, int(round(2000 * scale)))
         d = max(2, int(round(5000 * scale)))
-        return transport_lp(s, d, seed=BASE_SEED + 4, name="c4")
+        return transport_lp(s, d, seed=BASE_SEED + 4, name="transport10m")
     raise KeyError(name)

@@ -88,7 +88,7 @@ def _create(lib, lp, ws=256, **opt):
 
 
 def _bad(mutate):
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     lp = lpgen.LP(lp.name, lp.m1, lp.m2, lp.n, lp.rowptr.copy(), lp.colidx.copy(), lp.val.copy(),
                   lp.b.copy(), lp.c.copy(), lp.l.copy(), lp.u.copy())
     mutate(lp)

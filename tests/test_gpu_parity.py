@@ -46,11 +46,11 @@ def _iterate_parity(lp, iters=100, **sched):
 
 
 @pytest.mark.parametrize("sched", [{}, STRESS], ids=["default", "stress"])
-def test_c0_iterate_parity_100(sched):
-    _iterate_parity(lpgen.make("c0"), **sched)
+def test_tiny_iterate_parity_100(sched):
+    _iterate_parity(lpgen.make("tiny"), **sched)
 
 
-@pytest.mark.parametrize("name,scale", [("c1", 0.004), ("c4", 0.01)])
+@pytest.mark.parametrize("name,scale", [("zipf1m", 0.004), ("transport10m", 0.01)])
 @pytest.mark.parametrize("sched", [{}, STRESS], ids=["default", "stress"])
 def test_downscaled_iterate_parity(name, scale, sched):
     _iterate_parity(lpgen.make(name, scale), **sched)
@@ -58,7 +58,7 @@ def test_downscaled_iterate_parity(name, scale, sched):
 
 def test_iterate_parity_across_restarts():
     # 700 iterations: several checks, restarts and sigma updates on both sides
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     ref = oracle.solve(lp, max_iter=700)
     s = hprlp.Solver(lp, max_iter=700, lambda_override=ref.lam)
     sol = s.solve()
@@ -74,7 +74,7 @@ def test_iterate_parity_across_restarts():
 
 
 def test_power_method_lambda():
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     ref = oracle.solve(lp, max_iter=1)
     s = hprlp.Solver(lp, max_iter=1)
     s.solve()
@@ -83,13 +83,13 @@ def test_power_method_lambda():
     assert abs(st["power_iters"] - ref.power_iters) <= 2
 
 
-def test_c0_full_solve_parity():
-    lp = lpgen.make("c0")
+def test_tiny_full_solve_parity():
+    lp = lpgen.make("tiny")
     ref = oracle.solve(lp)
     s = hprlp.Solver(lp)
     sol = s.solve()
     st = sol.stats
-    print("c0 full", st["iters"], ref.iters, st["pobj"], ref.pobj, st["t_solve_ms"])
+    print("tiny full", st["iters"], ref.iters, st["pobj"], ref.pobj, st["t_solve_ms"])
     assert ref.status == "OPTIMAL" and sol.status == "OPTIMAL"
     assert max(st["rel_p"], st["rel_d"], st["rel_gap"]) <= 1e-8
     assert abs(st["pobj"] - ref.pobj) <= 1e-7 * (1 + abs(ref.pobj))
@@ -100,7 +100,7 @@ def test_c0_full_solve_parity():
 
 
 def test_deterministic_bitwise():
-    lp = lpgen.make("c1", 0.004)
+    lp = lpgen.make("zipf1m", 0.004)
     a = hprlp.Solver(lp, max_iter=600, **STRESS)
     sa = a.solve()
     b = hprlp.Solver(lp, max_iter=600, **STRESS)
@@ -111,7 +111,7 @@ def test_deterministic_bitwise():
 
 def test_outputs_to_device_pointers():
     import torch
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     s = hprlp.Solver(lp, max_iter=300)
     h = s.solve()
     x, y, z, st = s.solve_device()

@@ -22,7 +22,7 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("name,scale", [("c0", 1), ("c1", 0.004), ("c4", 0.01)])
+@pytest.mark.parametrize("name,scale", [("tiny", 1), ("zipf1m", 0.004), ("transport10m", 0.01)])
 @pytest.mark.parametrize("sched", [{}, STRESS], ids=["default", "stress"])
 def test_a32_iterate_parity_100(name, scale, sched):
     lp = lpgen.make(name, scale)
@@ -39,14 +39,14 @@ def test_a32_iterate_parity_100(name, scale, sched):
 
 
 def test_a32_power_method_lambda():
-    lp = lpgen.make("c1", 0.004)
+    lp = lpgen.make("zipf1m", 0.004)
     ref = oracle.solve(lp, max_iter=1)
     s = hprlp.Solver(lp, max_iter=1, precision=hprlp.FP64_A32)
     s.solve()
     assert abs(s.stats()["lambda"] - ref.lam) <= 1e-9 * ref.lam
 
 
-@pytest.mark.parametrize("name,scale", [("c0", 1), ("c1", 0.0005), ("c4", 0.02), ("c3", 0.004)])
+@pytest.mark.parametrize("name,scale", [("tiny", 1), ("zipf1m", 0.0005), ("transport10m", 0.02), ("batch256", 0.004)])
 def test_mixed_full_solve_against_oracle(name, scale):
     lp = lpgen.make(name, scale)
     if lp.inst_m1 is not None:
@@ -69,7 +69,7 @@ def test_mixed_full_solve_against_oracle(name, scale):
 
 def test_mixed_fp32_phase_tracks_oracle():
     # 100 FP32 iterations stay close to the FP64 iterates (FP32 rounding only)
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     ref = oracle.solve(lp, max_iter=100)
     s = hprlp.Solver(lp, max_iter=100, lambda_override=ref.lam, precision=hprlp.MIXED)
     s.solve()

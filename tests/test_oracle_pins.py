@@ -20,7 +20,7 @@ from lp_truth import dense_M, relative_kkt, support_box, vertex_enumeration
 
 # ----------------------------------------------------------------------------- generator
 
-@pytest.mark.parametrize("name,scale", [("c0", 1), ("c1", 0.004), ("c3", 0.01)])
+@pytest.mark.parametrize("name,scale", [("tiny", 1), ("zipf1m", 0.004), ("batch256", 0.01)])
 def test_generator_certificate_is_kkt(name, scale):
     lp = lpgen.make(name, scale)
     x, y, z = lp.cert.x, lp.cert.y, lp.cert.z
@@ -41,7 +41,7 @@ def test_generator_certificate_is_kkt(name, scale):
 
 
 def test_generator_fp32_exact_and_shapes():
-    lp = lpgen.make("c1", 0.004)
+    lp = lpgen.make("zipf1m", 0.004)
     assert np.all(lp.val.astype(np.float32).astype(np.float64) == lp.val)
     lens = np.diff(lp.rowptr)
     assert lens.min() >= 5 and lens.max() <= 40
@@ -50,7 +50,7 @@ def test_generator_fp32_exact_and_shapes():
         assert len(np.unique(cols)) == len(cols)
     free = ~np.isfinite(lp.l)
     assert 0.25 < free.mean() < 0.35
-    t = lpgen.make("c4", 0.01)
+    t = lpgen.make("transport10m", 0.01)
     assert t.b[:t.m1].sum() >= t.b[t.m1:].sum()
     assert np.all(np.diff(t.rowptr)[:t.m1] == 50) and np.all(np.diff(t.rowptr)[t.m1:] == 20)
 
@@ -68,9 +68,9 @@ def test_oracle_matches_vertex_enumeration(oracle_mod, seed):
     assert abs(r.pobj - best) <= 1e-8 * (1 + abs(best)), (r.pobj, best)
 
 
-def test_oracle_c0_matches_certificate_and_highs(oracle_mod):
+def test_oracle_tiny_matches_certificate_and_highs(oracle_mod):
     from scipy.optimize import linprog
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     r = oracle_mod.solve(lp)
     assert r.status == "OPTIMAL" and r.rel_kkt <= 1e-8
     assert abs(r.pobj - lp.cert.obj) <= 1e-7 * (1 + abs(lp.cert.obj))
@@ -86,7 +86,7 @@ def test_oracle_c0_matches_certificate_and_highs(oracle_mod):
     assert np.isclose(gap, r.rel_gap, rtol=1e-6, atol=1e-14)
 
 
-@pytest.mark.parametrize("name,scale", [("c1", 0.0005), ("c3", 0.004)])
+@pytest.mark.parametrize("name,scale", [("zipf1m", 0.0005), ("batch256", 0.004)])
 def test_oracle_downscaled_matches_certificate(oracle_mod, name, scale):
     lp = lpgen.make(name, scale)
     r = oracle_mod.solve(lp, max_iter=300000)
@@ -97,7 +97,7 @@ def test_oracle_downscaled_matches_certificate(oracle_mod, name, scale):
 def test_oracle_transport_matches_highs(oracle_mod):
     from scipy.optimize import linprog
     from scipy.sparse import csr_matrix
-    lp = lpgen.make("c4", 0.006)  # 12 x 30
+    lp = lpgen.make("transport10m", 0.006)  # 12 x 30
     A = csr_matrix((lp.val, lp.colidx, lp.rowptr), shape=(lp.m, lp.n))
     h = linprog(lp.c, A_ub=-A[lp.m1:], b_ub=-lp.b[lp.m1:], A_eq=A[:lp.m1], b_eq=lp.b[:lp.m1],
                 bounds=(0, None), method="highs")
@@ -185,7 +185,7 @@ def test_one_step_is_textbook_pdhg(oracle_mod):
     """With the Halpern step off and rho = 1 (no reflection), an iteration of eqs. update-x
     and update-y-2 is a Chambolle-Pock primal-dual step with primal step tau = sigma and dual
     step s = 1 / (lambda sigma) on min_x max_{y in D} <c,x> - <y, A x - b>."""
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     S, At = _scaled_dense(oracle_mod, lp)
     lam = float(np.linalg.eigvalsh(At @ At.T)[-1])
     sigma = 0.7
@@ -205,7 +205,7 @@ def test_one_step_is_textbook_pdhg(oracle_mod):
 
 def test_merit_equals_dense_M_norm(oracle_mod):
     """R~ = ||w - w_hat||_M with M written out densely from eq. def:M."""
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     S, At = _scaled_dense(oracle_mod, lp)
     lam = float(np.linalg.eigvalsh(At @ At.T)[-1])
     K = 23
@@ -222,7 +222,7 @@ def test_merit_equals_dense_M_norm(oracle_mod):
 def test_sigma_update_matches_eq_sigma(oracle_mod):
     """The first restart (k = 150) sets sigma = Delta_x / Delta_y; with a dense T1 this must
     equal sqrt(||dx||^2 / (||dy||^2_T1 + ||A^T dy||^2)) of eqs. sigma, Dx&Dy."""
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     S, At = _scaled_dense(oracle_mod, lp)
     a = oracle_mod.solve(lp, max_iter=150)
     b = oracle_mod.solve(lp, max_iter=151)
@@ -245,7 +245,7 @@ def test_halpern_bounds_prop23_thm24(oracle_mod):
        ||R(w_bar^{k+1})|| <= (sigma(||A||+||sqrt T1||)+1)/sqrt(sigma) R0/(k+1)  (Thm. 2.4)
     with w* the scaled certificate and lambda = lambda_1(A A^T) exactly; also x_bar in C and
     y_bar in D at every iteration (Section 4.1)."""
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     S, At = _scaled_dense(oracle_mod, lp)
     ev = np.linalg.eigvalsh(At @ At.T)
     lam = float(ev[-1])
@@ -269,7 +269,7 @@ def test_halpern_bounds_prop23_thm24(oracle_mod):
 # ----------------------------------------------------------------------------- control flow
 
 def test_first_restart_at_first_check_and_statuses(oracle_mod):
-    lp = lpgen.make("c0")
+    lp = lpgen.make("tiny")
     r = oracle_mod.solve(lp, max_iter=1)
     assert r.status == "ITER_LIMIT" and r.iters == 1
     r = oracle_mod.solve(lp, max_iter=1000)
