@@ -24,7 +24,8 @@
  *     +INFINITY.  They are copied.
  *   - Device memory: the library never allocates device memory.  The caller passes one
  *     device workspace of at least hprlp_workspace_bytes() bytes (256-byte aligned) and keeps
- *     it alive until hprlp_destroy.  All work is ordered on the caller's HIP stream.
+ *     it alive until hprlp_destroy.  All work of a single-LP handle is ordered on the
+ *     caller's HIP stream (a batched handle has a stream of its own, see below).
  *   - Output vectors (x, y, z, iterates) may be host or device pointers; the library detects
  *     which.  They are always in the ORIGINAL (unscaled) space of the problem as given.
  *   - Threads: one call at a time per handle; different handles are independent.
@@ -126,7 +127,7 @@ typedef enum {
     HPRLP_XBAR = 0,  /* x_bar of the last checked iteration (the returned primal)         */
     HPRLP_YBAR = 1,  /* y_bar of the last checked iteration (the returned dual, length m) */
     HPRLP_ZBAR = 2,  /* z_bar of the last checked iteration (eq. update-z)                */
-    HPRLP_XCUR = 3,  /* current iterate x^{r,t} after the last Halpern step               */
+    HPRLP_XCUR = 3,  /* current iterate x^{r,t} after the last Halpern step (single LP)   */
     HPRLP_YCUR = 4,  /* current iterate y^{r,t}                                           */
     HPRLP_DROW = 5,  /* row scaling D_r (length m; A~ = D_r A D_c)                        */
     HPRLP_DCOL = 6   /* column scaling D_c (length n)                                     */
@@ -154,15 +155,57 @@ int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
                  const double *b, const double *c, const double *l, const double *u,
                  const hprlp_options *opt, void *d_workspace, size_t ws_bytes, void *stream);
 
+/* Workspace bound for a batch of n_inst LPs packed block-diagonally into m rows, n columns
+ * and nnz nonzeros (see hprlp_create_batched).  Host only; EDIM on bad sizes
+ * (n_inst must be in [1, min(m, n)]). */
+int hprlp_workspace_bytes_batched(int32_t n_inst, int64_t m, int64_t n, int64_t nnz,
+                                  const hprlp_options *opt, size_t *bytes);
+
+/* Create a handle that solves n_inst independent LPs (each of the form eq. primalLP) in one
+ * run.  The LPs are packed block-diagonally into one CSR: instance i owns rows
+ * [inst_row_off[i], inst_row_off[i+1]) and columns [inst_col_off[i], inst_col_off[i+1]);
+ * inside its rows, its first inst_m1[i] rows are equalities and the rest inequalities;
+ * no row may have a nonzero outside its instance's columns (EDIM otherwise).  rowptr,
+ * colidx, val, b, c, l, u are as for hprlp_create over the packed problem; inst_row_off and
+ * inst_col_off are int64[n_inst + 1] host arrays starting at 0 and ending at m and n, strictly
+ * increasing (every instance has a row, a column and a nonzero).  lambda_inst (host,
+ * double[n_inst], nullable): lambda of every instance; NULL: lambda_override if > 0, else the
+ * power method run on all instances at once.
+ * Every instance is solved exactly as hprlp_create + hprlp_solve would solve it alone
+ * (its own preconditioning is the restriction of the packed one, since Ruiz and
+ * Pock-Chambolle scale rows and columns independently; its own beta_b, beta_c, sigma,
+ * lambda, restart counters and termination test, Sections 3.1, 3.2 and 4.1), except that:
+ * check_every must be >= 2; the columns are never renumbered (reorder is ignored); a MIXED
+ * batch switches every instance to FP64 together, when all instances still iterating have
+ * reached tol_switch or the largest rel. KKT among them stalls (stall_checks); and
+ * max_iter / time_limit are tested every check_every iterations.  An instance that
+ * terminates stops iterating; its returned w_bar is that of its last check.
+ * Work runs on a stream owned by the handle (the caller's `stream` is synchronised at
+ * create and at every solve); each check_every-iteration chunk is one captured hipGraph. */
+int hprlp_create_batched(hprlp_handle **out, int32_t n_inst, const int64_t *inst_row_off,
+                         const int64_t *inst_col_off, const int64_t *inst_m1,
+                         const int64_t *rowptr, const int32_t *colidx, const double *val,
+                         const double *b, const double *c, const double *l, const double *u,
+                         const double *lambda_inst, const hprlp_options *opt,
+                         void *d_workspace, size_t ws_bytes, void *stream);
+
 /* Run Algorithm 2 from the origin (Section 4.1) until the relative KKT residual of w_bar
  * is <= tol at a check, or a limit is hit.  lambda = lambda_1(A~ A~^T) by the power
  * method unless overridden (T1 = lambda I - A~ A~^T, Section 3.2).  Writes the returned
  * w_bar = (x, y, z) in the original space (x: n, y: m, z: n; any may be NULL) and *status.
- * The call blocks until the result is ready. */
+ * The call blocks until the result is ready.  Batched handle: every instance is solved;
+ * *status is OPTIMAL only if every instance is, else the first other status met. */
 int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int *status);
 
-/* Statistics of the last solve. */
+/* Statistics of the last solve.  Batched handle: iters = iterations run, restarts summed,
+ * residuals the largest over the instances, objectives summed; per-instance figures come
+ * from hprlp_stats_instance. */
 int hprlp_stats(const hprlp_handle *h, hprlp_stats_t *out);
+
+/* Statistics of instance i (0 <= i < n_inst; a single-LP handle has instance 0 only) of
+ * the last solve: its own iters (iterations until it stopped), restarts, sigma, lambda,
+ * residuals, objectives, beta_b, beta_c, n_checks and status.  ESTATE before a solve. */
+int hprlp_stats_instance(const hprlp_handle *h, int32_t i, hprlp_stats_t *out);
 
 /* Copy one iterate (hprlp_iterate) of the last solve into out (host or device pointer,
  * length n or m). */
@@ -173,6 +216,13 @@ int hprlp_get_iterate(const hprlp_handle *h, int which, double *out);
  *  Delta_x, Delta_y, err_p, err_d, restarted, sigma_next).  Copies at most cap rows into
  * out (host) and writes the total row count to *n_rows. */
 int hprlp_get_trace(const hprlp_handle *h, double *out, long long cap, long long *n_rows);
+
+/* Check trace of instance i of a batched solve, kept on the device for its first 64
+ * checks: rows of 10 doubles (k, t, r, sigma, merit, rel_p, rel_d, rel_gap, restarted,
+ * sigma_next).  Copies at most cap rows into out (host) and writes min(checks, 64) to
+ * *n_rows.  EINVAL on a single-LP handle. */
+int hprlp_get_trace_instance(const hprlp_handle *h, int32_t i, double *out, long long cap,
+                             long long *n_rows);
 
 /* Time the two iteration passes on the current state: `reps` launches of the column pass
  * (x-step over A~^T) and of the row pass (y-step over A~), each bracketed by HIP events on

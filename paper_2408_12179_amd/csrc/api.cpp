@@ -1,8 +1,12 @@
 // C ABI and host driver of the HPR-LP library (Algorithm 2 of the paper).
 //
-// The iteration runs entirely in the HIP kernels (kernels.hip); the host launches them and,
-// every check_every iterations (Section 4.1), reads back a dozen reduced FP64 scalars to take
-// the termination, restart (Section 3.1) and sigma (Section 3.2, Algorithm 3) decisions.
+// The iteration runs entirely in the HIP kernels (kernels.hip).  For one LP the host
+// launches them and, every check_every iterations (Section 4.1), reads back a dozen reduced
+// FP64 scalars to take the termination, restart (Section 3.1) and sigma (Section 3.2,
+// Algorithm 3) decisions.  For a batch of LPs packed block-diagonally the same decisions are
+// taken per instance on the device, and a whole chunk of check_every iterations (passes,
+// check passes, decisions, restart copies) is one hipGraph launch; the host reads back only
+// four summary numbers per chunk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,19 +53,36 @@ struct Carver {
     template <class T> T *arr(size_t n) { return static_cast<T *>(take(n * sizeof(T))); }
 };
 
+// Device arrays of a batched solve (one entry per instance unless noted).
+struct BatchDev {
+    double *sigma = nullptr, *lam = nullptr, *merit0 = nullptr, *merit_prev = nullptr;
+    long long *kstart = nullptr, *kbase = nullptr /*[1]*/, *iters_done = nullptr;
+    long long *restarts = nullptr, *nchecks = nullptr;
+    int *m1_end = nullptr, *active = nullptr, *status = nullptr, *restart_flag = nullptr;
+    int *row_off = nullptr, *col_off = nullptr;   // [n_inst + 1]
+    double *inv_norm = nullptr, *cst = nullptr /*[n][8]*/, *last = nullptr /*[n][6]*/;
+    double *res_first = nullptr, *res_chk = nullptr;  // [n][2][kNQ]
+    double *trace = nullptr;                          // [n][kTraceRows][kTraceCols]
+    double *summary = nullptr;                        // [4]
+    double *seg_tmp = nullptr;                        // [2n]
+    int *segA_ptr = nullptr, *segA_slots = nullptr, *segT_ptr = nullptr, *segT_slots = nullptr;
+};
+
 }  // namespace
 
 struct hprlp_handle {
     hprlp_options opt{};
     int64_t m1 = 0, m2 = 0, m = 0, n = 0, nnz = 0;
-    bool mixed = false;   // A stored in FP32 (original values) with the scaling folded
+    bool mixed = false;     // A stored in FP32 (original values) with the scaling folded
     bool f32phase = false;  // MIXED: starts with FP32 vectors
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;       // stream all library work is ordered on
+    hipStream_t user_st = nullptr;  // the caller's stream
+    bool own_stream = false;
     DevMat A, T;
     VecSet<double> v64;
     VecSet<float> v32;
     CheckData chk;
-    double *ux = nullptr, *uy = nullptr;     // unscaling of x and y (FP64 mode: vectors)
+    double *ux = nullptr, *uy = nullptr;     // unscaling of x and y
     int *cperm = nullptr;                   // column renumbering: internal j -> caller's column
     double *vg = nullptr, *w = nullptr, *hist = nullptr, *inv_norm = nullptr;
     double *partsA = nullptr, *partsT = nullptr;
@@ -71,7 +92,16 @@ struct hprlp_handle {
     size_t pinned_len = 0;
     double beta_b = 1, beta_c = 1, bnorm = 0, cnorm = 0, bsnorm = 0, csnorm = 0;
     std::vector<double> dr, dc;
-    // solve state
+    // batched solve
+    bool batched = false;
+    int n_inst = 1;
+    std::vector<int64_t> row_off;           // instance row offsets (host copy)
+    BatchDev bd;
+    Segments segA, segT;
+    std::vector<double> lam_given;          // per-instance lambda from the caller (or empty)
+    hipGraphExec_t graphs[3] = {nullptr, nullptr, nullptr};
+    std::vector<hprlp_stats_t> inst_stats;
+    // solve state (single LP)
     int prec = 0;
     long long t = 0, k = 0, r = 0;
     double sigma = 1, lambda = 0;
@@ -103,6 +133,8 @@ struct Plan {
     bool mixed, f32phase;
     int itemsA, itemsT, splitA, splitT, slotsA, slotsT;
     int power_cap;
+    int n_inst;
+    bool batched;
 };
 
 void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
@@ -146,12 +178,34 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     double *ux = cv.arr<double>(n), *uy = cv.arr<double>(m);
     int *cperm = cv.arr<int>(n);
     double *vg = cv.arr<double>(m), *w = cv.arr<double>(n);
-    double *hist = cv.arr<double>((size_t)p.power_cap);
-    double *inv_norm = cv.arr<double>(1);
+    const size_t ni = (size_t)p.n_inst;
+    double *hist = cv.arr<double>((size_t)p.power_cap * ni);
+    double *inv_norm = cv.arr<double>(ni);
     double *partsA = cv.arr<double>((size_t)(p.itemsA + p.splitA + 1) * kNQ);
     double *partsT = cv.arr<double>((size_t)(p.itemsT + p.splitT + 1) * kNQ);
     double *res = cv.arr<double>(4 * kNQ);
     double *outv = cv.arr<double>(2 * n + m);
+    BatchDev b;
+    if (p.batched) {
+        b.sigma = cv.arr<double>(ni); b.lam = cv.arr<double>(ni);
+        b.merit0 = cv.arr<double>(ni); b.merit_prev = cv.arr<double>(ni);
+        b.kstart = cv.arr<long long>(ni); b.kbase = cv.arr<long long>(1);
+        b.iters_done = cv.arr<long long>(ni); b.restarts = cv.arr<long long>(ni);
+        b.nchecks = cv.arr<long long>(ni);
+        b.m1_end = cv.arr<int>(ni); b.active = cv.arr<int>(ni); b.status = cv.arr<int>(ni);
+        b.restart_flag = cv.arr<int>(ni);
+        b.row_off = cv.arr<int>(ni + 1); b.col_off = cv.arr<int>(ni + 1);
+        b.inv_norm = inv_norm;
+        b.cst = cv.arr<double>(ni * 8); b.last = cv.arr<double>(ni * 6);
+        b.res_first = cv.arr<double>(ni * 2 * kNQ); b.res_chk = cv.arr<double>(ni * 2 * kNQ);
+        b.trace = cv.arr<double>(ni * kTraceRows * kTraceCols);
+        b.summary = cv.arr<double>(4);
+        b.seg_tmp = cv.arr<double>(2 * ni);
+        b.segA_ptr = cv.arr<int>(ni + 1);
+        b.segA_slots = cv.arr<int>((size_t)(p.itemsA + p.splitA + 1));
+        b.segT_ptr = cv.arr<int>(ni + 1);
+        b.segT_slots = cv.arr<int>((size_t)(p.itemsT + p.splitT + 1));
+    }
     if (h) {
         h->A.rp = A.rp; h->A.ci = A.ci; h->A.va = A.va; h->A.items = A.items;
         h->A.splits = A.splits; h->A.split_part = A.split_part;
@@ -161,6 +215,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         h->cperm = cperm;
         h->hist = hist; h->inv_norm = inv_norm; h->partsA = partsA; h->partsT = partsT;
         h->res = res; h->outv = outv;
+        h->bd = b;
     }
 }
 
@@ -173,8 +228,11 @@ size_t plan_bytes(const Plan &p) {
 }
 
 // Worst-case item counts of a schedule over `rows` rows (see build_schedule): tiles plus
-// long rows plus split rows are at most `rows`; chunks at most nnz/chunk + split rows.
-Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o) {
+// long rows plus split rows are at most `rows`; chunks at most nnz/chunk + split rows.  A
+// batched schedule closes tiles at instance boundaries, which adds at most one tile per
+// instance (already inside the 2 * rows bound, as every instance has a row).
+Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n_inst,
+                bool batched) {
     Plan p;
     p.m = m; p.n = n; p.nnz = nnz; p.mixed = o.precision != HPRLP_FP64;
     p.f32phase = o.precision == HPRLP_MIXED;
@@ -188,6 +246,8 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o) {
     p.slotsA = (int)ch + p.splitA;
     p.slotsT = (int)ch + p.splitT;
     p.power_cap = power_cap(o);
+    p.n_inst = n_inst;
+    p.batched = batched;
     return p;
 }
 
@@ -195,6 +255,13 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o) {
 template <class T> int upload(hprlp_handle *h, T *dst, const T *src, size_t n) {
     if (n == 0) return HPRLP_OK;
     HIPCHK(h, hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return HPRLP_OK;
+}
+
+template <class T> int download(hprlp_handle *h, T *dst, const T *src, size_t n) {
+    if (n == 0) return HPRLP_OK;
+    HIPCHK(h, hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     return HPRLP_OK;
 }
@@ -208,30 +275,54 @@ hipEvent_t pool_event(hprlp_handle *h, size_t idx) {
     return h->ev_pool[idx];
 }
 
-}  // namespace
+// Slots of every instance (work items of the main kernel, then split-row finishers), in slot
+// order: the check sums of an instance are added in this fixed order.
+void build_segments(const Schedule &s, int n_inst, std::vector<int> &ptr,
+                    std::vector<int> &slots) {
+    std::vector<std::vector<int>> per(n_inst);
+    for (size_t p = 0; p < s.items.size(); ++p) {
+        const int4 it = s.items[p];
+        const int kind = it.w & 3;
+        int inst = -1;
+        if (kind == IT_TILE || kind == IT_CHUNK) inst = it.z;
+        else if (kind == IT_ROW) inst = it.w >> 2;
+        if (inst >= 0) per[inst].push_back((int)p);
+    }
+    for (size_t q = 0; q < s.splits.size(); ++q)
+        per[s.splits[q].w].push_back((int)(s.items.size() + q));
+    ptr.assign(n_inst + 1, 0);
+    slots.clear();
+    for (int b = 0; b < n_inst; ++b) {
+        slots.insert(slots.end(), per[b].begin(), per[b].end());
+        ptr[b + 1] = (int)slots.size();
+    }
+}
 
-namespace {
+// Instance structure of a problem (a single LP is one instance).
+struct Layout {
+    int n_inst;
+    std::vector<int64_t> row_off, col_off, m1;
+    bool batched;
+};
 
-// Device part of hprlp_create: upload matrices (int32 row pointers), schedules, data
-// vectors in the pass coordinates, check multipliers and unscaling vectors.
-int create_device(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
-                  const double *val, const double *b, const double *c, const double *l,
-                  const double *u, const std::vector<int64_t> &rpt,
+// Device part of create: upload matrices (int32 row pointers), schedules, data vectors in
+// the pass coordinates, check multipliers, unscaling vectors and per-instance constants.
+int create_device(hprlp_handle *h, const Layout &L, const int64_t *rowptr,
+                  const int32_t *colidx, const double *val, const double *b, const double *c,
+                  const double *l, const double *u, const std::vector<int64_t> &rpt,
                   const std::vector<int32_t> &cit, const std::vector<int32_t> &pos,
-                  const Scaling &sc, const std::vector<double> &bs,
-                  const std::vector<double> &cs, const std::vector<int32_t> &order) {
+                  const Scaling &sc, const std::vector<int32_t> &order,
+                  const std::vector<int32_t> &inst_row, const std::vector<int32_t> &inst_col,
+                  const std::vector<std::array<double, 8>> &cst) {
     const hprlp_options &o = h->opt;
     const int64_t m = h->m, n = h->n, nnz = h->nnz;
-    const double bb = h->beta_b, bc = h->beta_c;
     int rc;
-    // ---- upload: matrices (int32 row pointers), schedules, data vectors
     {
         std::vector<int> rp32((size_t)std::max(m, n) + 1);
         for (int64_t i = 0; i <= m; ++i) rp32[i] = (int)rowptr[i];
         if ((rc = upload(h, h->A.rp, rp32.data(), (size_t)m + 1))) return rc;
         for (int64_t j = 0; j <= n; ++j) rp32[j] = (int)rpt[j];
         if ((rc = upload(h, h->T.rp, rp32.data(), (size_t)n + 1))) return rc;
-        HIPCHK(h, hipStreamSynchronize(h->st));
     }
     if ((rc = upload(h, h->cperm, order.data(), (size_t)n))) return rc;
     if ((rc = upload(h, h->A.ci, colidx, (size_t)nnz))) return rc;
@@ -240,182 +331,202 @@ int create_device(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
         std::vector<float> f((size_t)nnz);
         for (int64_t q = 0; q < nnz; ++q) f[q] = (float)val[q];
         if ((rc = upload(h, (float *)h->A.va, f.data(), (size_t)nnz))) return rc;
-        HIPCHK(h, hipStreamSynchronize(h->st));
         for (int64_t q = 0; q < nnz; ++q) f[q] = (float)val[pos[q]];
         if ((rc = upload(h, (float *)h->T.va, f.data(), (size_t)nnz))) return rc;
-        HIPCHK(h, hipStreamSynchronize(h->st));
     } else {
         if ((rc = upload(h, (double *)h->A.va, sc.val.data(), (size_t)nnz))) return rc;
         std::vector<double> vt((size_t)nnz);
         for (int64_t q = 0; q < nnz; ++q) vt[q] = sc.val[pos[q]];
         if ((rc = upload(h, (double *)h->T.va, vt.data(), (size_t)nnz))) return rc;
-        HIPCHK(h, hipStreamSynchronize(h->st));
     }
     for (DevMat *M : {&h->A, &h->T}) {
-        if ((rc = upload(h, M->items, M->host.items.data(), M->host.items.size())))
-            return rc;
+        if ((rc = upload(h, M->items, M->host.items.data(), M->host.items.size()))) return rc;
         if ((rc = upload(h, M->splits, M->host.splits.data(), M->host.splits.size())))
             return rc;
     }
-    // data vectors in the pass coordinates, plus check multipliers and unscaling
-    {
-        std::vector<double> cd(n), ld(n), ud(n), bd(m), co(n), csv(n), xs(n), ro(m), rs(m),
-            ys(m), ux(n), uy(m), sc2, sr2;
-        for (int64_t j = 0; j < n; ++j) {
-            const double d = sc.dc[j];
-            if (h->mixed) {  // x' = D_c x~ = x / beta_b
-                cd[j] = c[j] / bc;
-                ld[j] = l[j] / bb;
-                ud[j] = u[j] / bb;
-                co[j] = bc / (d * d);
-                csv[j] = 1.0 / d;
-                xs[j] = 1.0 / d;
-                ux[j] = bb;
-            } else {         // scaled problem of Section 4.1
-                cd[j] = cs[j];
-                ld[j] = l[j] / d / bb;
-                ud[j] = u[j] / d / bb;
-                co[j] = bc / d;
-                csv[j] = 1.0;
-                xs[j] = 1.0;
-                ux[j] = bb * d;
-            }
+    // data vectors in the pass coordinates, check multipliers and unscaling; every row and
+    // column uses the normalisation factors beta_b, beta_c of its own instance
+    std::vector<double> cd(n), ld(n), ud(n), bd(m), co(n), csv(n), xs(n), ro(m), rs(m), ys(m),
+        ux(n), uy(m), sc2, sr2;
+    for (int64_t j = 0; j < n; ++j) {
+        const double d = sc.dc[j], bb = cst[inst_col[j]][0], bc = cst[inst_col[j]][1];
+        if (h->mixed) {  // x' = D_c x~ = x / beta_b
+            cd[j] = c[j] / bc;
+            ld[j] = l[j] / bb;
+            ud[j] = u[j] / bb;
+            co[j] = bc / (d * d);
+            csv[j] = 1.0 / d;
+            xs[j] = 1.0 / d;
+            ux[j] = bb;
+        } else {         // scaled problem of Section 4.1
+            cd[j] = d * c[j] / bc;
+            ld[j] = l[j] / d / bb;
+            ud[j] = u[j] / d / bb;
+            co[j] = bc / d;
+            csv[j] = 1.0;
+            xs[j] = 1.0;
+            ux[j] = bb * d;
         }
-        for (int64_t i = 0; i < m; ++i) {
-            const double d = sc.dr[i];
-            if (h->mixed) {  // y' = D_r y~ = y / beta_c
-                bd[i] = b[i] / bb;
-                ro[i] = bb;
-                rs[i] = d;
-                ys[i] = 1.0 / d;
-                uy[i] = bc;
-            } else {
-                bd[i] = bs[i];
-                ro[i] = bb / d;
-                rs[i] = 1.0;
-                ys[i] = 1.0;
-                uy[i] = bc * d;
-            }
-        }
-        auto up = [&](double *dst, const std::vector<double> &v) {
-            return upload(h, dst, v.data(), v.size());
-        };
-        if ((rc = up(h->v64.cd, cd)) || (rc = up(h->v64.ld, ld)) || (rc = up(h->v64.ud, ud)) ||
-            (rc = up(h->v64.bd, bd)) || (rc = up(h->chk.co, co)) || (rc = up(h->chk.cs, csv)) ||
-            (rc = up(h->chk.xs, xs)) || (rc = up(h->chk.ro, ro)) || (rc = up(h->chk.rs, rs)) ||
-            (rc = up(h->chk.ys, ys)) || (rc = up(h->ux, ux)) || (rc = up(h->uy, uy)))
-            return rc;
-        if ((rc = upload(h, h->chk.lo, l, (size_t)n)) || (rc = upload(h, h->chk.uo, u, (size_t)n)))
-            return rc;
-        HIPCHK(h, hipStreamSynchronize(h->st));
-        if (h->mixed) {
-            sc2.resize(n);
-            sr2.resize(m);
-            for (int64_t j = 0; j < n; ++j) sc2[j] = sc.dc[j] * sc.dc[j];
-            for (int64_t i = 0; i < m; ++i) sr2[i] = sc.dr[i] * sc.dr[i];
-            if ((rc = up(h->v64.sc, sc2)) || (rc = up(h->v64.sr, sr2))) return rc;
-        }
-        if (h->f32phase) {
-            auto upf = [&](float *dst, const std::vector<double> &v) {
-                std::vector<float> f(v.size());
-                for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
-                int r2 = upload(h, dst, f.data(), f.size());
-                if (r2) return r2;
-                HIPCHK(h, hipStreamSynchronize(h->st));
-                return (int)HPRLP_OK;
-            };
-            if ((rc = upf(h->v32.cd, cd)) || (rc = upf(h->v32.ld, ld)) ||
-                (rc = upf(h->v32.ud, ud)) || (rc = upf(h->v32.bd, bd)) ||
-                (rc = upf(h->v32.sc, sc2)) || (rc = upf(h->v32.sr, sr2)))
-                return rc;
-        }
-        HIPCHK(h, hipStreamSynchronize(h->st));
     }
-    h->pinned_len = std::max<size_t>(4 * kNQ + 64, (size_t)power_cap(o));
+    for (int64_t i = 0; i < m; ++i) {
+        const double d = sc.dr[i], bb = cst[inst_row[i]][0], bc = cst[inst_row[i]][1];
+        if (h->mixed) {  // y' = D_r y~ = y / beta_c
+            bd[i] = b[i] / bb;
+            ro[i] = bb;
+            rs[i] = d;
+            ys[i] = 1.0 / d;
+            uy[i] = bc;
+        } else {
+            bd[i] = d * b[i] / bb;
+            ro[i] = bb / d;
+            rs[i] = 1.0;
+            ys[i] = 1.0;
+            uy[i] = bc * d;
+        }
+    }
+    auto up = [&](double *dst, const std::vector<double> &v) {
+        return upload(h, dst, v.data(), v.size());
+    };
+    if ((rc = up(h->v64.cd, cd)) || (rc = up(h->v64.ld, ld)) || (rc = up(h->v64.ud, ud)) ||
+        (rc = up(h->v64.bd, bd)) || (rc = up(h->chk.co, co)) || (rc = up(h->chk.cs, csv)) ||
+        (rc = up(h->chk.xs, xs)) || (rc = up(h->chk.ro, ro)) || (rc = up(h->chk.rs, rs)) ||
+        (rc = up(h->chk.ys, ys)) || (rc = up(h->ux, ux)) || (rc = up(h->uy, uy)))
+        return rc;
+    if ((rc = upload(h, h->chk.lo, l, (size_t)n)) || (rc = upload(h, h->chk.uo, u, (size_t)n)))
+        return rc;
+    if (h->mixed) {
+        sc2.resize(n);
+        sr2.resize(m);
+        for (int64_t j = 0; j < n; ++j) sc2[j] = sc.dc[j] * sc.dc[j];
+        for (int64_t i = 0; i < m; ++i) sr2[i] = sc.dr[i] * sc.dr[i];
+        if ((rc = up(h->v64.sc, sc2)) || (rc = up(h->v64.sr, sr2))) return rc;
+    }
+    if (h->f32phase) {
+        auto upf = [&](float *dst, const std::vector<double> &v) {
+            std::vector<float> f(v.size());
+            for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+            return upload(h, dst, f.data(), f.size());
+        };
+        if ((rc = upf(h->v32.cd, cd)) || (rc = upf(h->v32.ld, ld)) || (rc = upf(h->v32.ud, ud)) ||
+            (rc = upf(h->v32.bd, bd)) || (rc = upf(h->v32.sc, sc2)) || (rc = upf(h->v32.sr, sr2)))
+            return rc;
+    }
+    if (L.batched) {
+        const int ni = L.n_inst;
+        std::vector<int> ro32(ni + 1), co32(ni + 1), m1e(ni);
+        std::vector<double> cstf((size_t)ni * 8);
+        for (int bi = 0; bi <= ni; ++bi) {
+            ro32[bi] = (int)L.row_off[bi];
+            co32[bi] = (int)L.col_off[bi];
+        }
+        for (int bi = 0; bi < ni; ++bi) {
+            m1e[bi] = (int)(L.row_off[bi] + L.m1[bi]);
+            for (int q = 0; q < 8; ++q) cstf[(size_t)bi * 8 + q] = cst[bi][q];
+        }
+        std::vector<int> ptr, slots;
+        if ((rc = upload(h, h->bd.row_off, ro32.data(), ro32.size())) ||
+            (rc = upload(h, h->bd.col_off, co32.data(), co32.size())) ||
+            (rc = upload(h, h->bd.m1_end, m1e.data(), m1e.size())) ||
+            (rc = upload(h, h->bd.cst, cstf.data(), cstf.size())))
+            return rc;
+        build_segments(h->A.host, ni, ptr, slots);
+        if ((rc = upload(h, h->bd.segA_ptr, ptr.data(), ptr.size())) ||
+            (rc = upload(h, h->bd.segA_slots, slots.data(), slots.size())))
+            return rc;
+        build_segments(h->T.host, ni, ptr, slots);
+        if ((rc = upload(h, h->bd.segT_ptr, ptr.data(), ptr.size())) ||
+            (rc = upload(h, h->bd.segT_slots, slots.data(), slots.size())))
+            return rc;
+        h->segA = Segments{h->bd.segA_ptr, h->bd.segA_slots, ni};
+        h->segT = Segments{h->bd.segT_ptr, h->bd.segT_slots, ni};
+    }
+    h->pinned_len = std::max<size_t>(4 * kNQ + 64, (size_t)power_cap(o) * L.n_inst);
     HIPCHK(h, hipHostMalloc((void **)&h->pinned, h->pinned_len * sizeof(double), 0));
     return HPRLP_OK;
 }
 
-}  // namespace
-
-// ============================================================================ C ABI
-
-extern "C" void hprlp_default_options(hprlp_options *o) {
-    if (!o) return;
-    std::memset(o, 0, sizeof(*o));
-    o->tol = 1e-8;
-    o->check_every = 150;
-    o->max_iter = 10000000;
-    o->time_limit = 0;
-    o->alpha1 = 0.2;
-    o->alpha2 = 0.6;
-    o->alpha3 = 0.2;
-    o->sigma0 = 1.0;
-    o->ruiz_iters = 10;
-    o->pock_chambolle = 1;
-    o->normalize_bc = 1;
-    o->power_max_iter = 5000;
-    o->power_tol = 1e-10;
-    o->lambda_override = 0;
-    o->use_halpern = 1;
-    o->use_restart = 1;
-    o->sigma_update = 1;
-    o->precision = HPRLP_FP64;
-    o->tol_switch = 1e-5;
-    o->stall_checks = 10;
-    o->reorder = 1;
-    o->profile = 0;
-    o->verbose = 0;
-    resolve_options(*o);
-}
-
-extern "C" int hprlp_workspace_bytes(int64_t m1, int64_t m2, int64_t n, int64_t nnz,
-                                     const hprlp_options *opt, size_t *bytes) {
-    hprlp_options o;
-    if (opt) o = *opt;
-    else hprlp_default_options(&o);
-    resolve_options(o);
-    if (!bytes) return fail(nullptr, HPRLP_EINVAL, "bytes is null");
-    if (m1 < 0 || m2 < 0 || m1 + m2 < 1 || n < 1 || nnz < 1 || nnz >= (1LL << 31))
-        return fail(nullptr, HPRLP_EDIM, "bad dimensions");
-    std::string err;
-    int rc = validate_options(o, err);
-    if (rc) return fail(nullptr, rc, err);
-    *bytes = plan_bytes(bound_plan(m1 + m2, n, nnz, o));
+// Block structure of a batched problem (host only, after validate_problem).
+int validate_layout(const Layout &L, int64_t m, int64_t n, const int64_t *rowptr,
+                    const int32_t *colidx, std::string &err) {
+    const int ni = L.n_inst;
+    if (L.row_off[0] != 0 || L.col_off[0] != 0 || L.row_off[ni] != m || L.col_off[ni] != n) {
+        err = "instance offsets must start at 0 and end at m and n";
+        return HPRLP_EDIM;
+    }
+    for (int b = 0; b < ni; ++b) {
+        if (L.row_off[b + 1] <= L.row_off[b] || L.col_off[b + 1] <= L.col_off[b]) {
+            err = "instance " + std::to_string(b) + " has no rows or no columns";
+            return HPRLP_EDIM;
+        }
+        if (L.m1[b] < 0 || L.m1[b] > L.row_off[b + 1] - L.row_off[b]) {
+            err = "instance " + std::to_string(b) + ": m1 out of range";
+            return HPRLP_EDIM;
+        }
+        if (rowptr[L.row_off[b + 1]] == rowptr[L.row_off[b]]) {
+            err = "instance " + std::to_string(b) + " has an empty matrix";
+            return HPRLP_EDIM;
+        }
+        for (int64_t i = L.row_off[b]; i < L.row_off[b + 1]; ++i)
+            for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+                if (colidx[p] < L.col_off[b] || colidx[p] >= L.col_off[b + 1]) {
+                    err = "row " + std::to_string(i) + " reaches outside its instance's columns";
+                    return HPRLP_EDIM;
+                }
+    }
     return HPRLP_OK;
 }
 
-extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
-                            const int64_t *rowptr, const int32_t *colidx, const double *val,
-                            const double *b, const double *c, const double *l, const double *u,
-                            const hprlp_options *opt, void *d_workspace, size_t ws_bytes,
-                            void *stream) {
+// Shared body of hprlp_create and hprlp_create_batched.
+int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
+                const int32_t *colidx, const double *val, const double *b, const double *c,
+                const double *l, const double *u, const double *lambda_inst,
+                const hprlp_options *opt, void *d_workspace, size_t ws_bytes, void *stream) {
     if (!out) return fail(nullptr, HPRLP_EINVAL, "out is null");
     *out = nullptr;
     hprlp_options o;
     if (opt) o = *opt;
     else hprlp_default_options(&o);
     resolve_options(o);
+    if (L.batched) o.reorder = 0;  // instances keep their own contiguous column blocks
     std::string err;
     int rc = validate_options(o, err);
     if (rc) return fail(nullptr, rc, err);
-    rc = validate_problem(m1, m2, n, rowptr, colidx, val, b, c, l, u, o, err);
+    if (L.batched && o.check_every < 2)
+        return fail(nullptr, HPRLP_EINVAL, "batched solves need check_every >= 2");
+    const int64_t m = L.row_off[L.n_inst], n = L.col_off[L.n_inst];
+    int64_t m1tot = 0;
+    for (int bi = 0; bi < L.n_inst; ++bi) m1tot += L.m1[bi];
+    rc = validate_problem(L.batched ? m : L.m1[0], L.batched ? 0 : m - L.m1[0], n, rowptr,
+                          colidx, val, b, c, l, u, o, err);
     if (rc) return fail(nullptr, rc, err);
+    if (L.batched && (rc = validate_layout(L, m, n, rowptr, colidx, err)))
+        return fail(nullptr, rc, err);
+    if (lambda_inst)
+        for (int bi = 0; bi < L.n_inst; ++bi)
+            if (!(lambda_inst[bi] > 0.0) || !std::isfinite(lambda_inst[bi]))
+                return fail(nullptr, HPRLP_EINVAL, "lambda values must be positive and finite");
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255))
         return fail(nullptr, HPRLP_EINVAL, "workspace must be a non-null 256-byte aligned device pointer");
 
-    const int64_t m = m1 + m2, nnz = rowptr[m];
+    const int64_t nnz = rowptr[m];
     hprlp_handle *h = new (std::nothrow) hprlp_handle();
     if (!h) return fail(nullptr, HPRLP_ENOMEM, "handle allocation failed");
-    h->opt = o; h->m1 = m1; h->m2 = m2; h->m = m; h->n = n; h->nnz = nnz;
+    h->opt = o; h->m = m; h->n = n; h->nnz = nnz;
+    h->m1 = L.batched ? m1tot : L.m1[0];
+    h->m2 = m - h->m1;
     h->mixed = o.precision != HPRLP_FP64;
     h->f32phase = o.precision == HPRLP_MIXED;
-    h->st = static_cast<hipStream_t>(stream);
+    h->batched = L.batched;
+    h->n_inst = L.n_inst;
+    h->row_off = L.row_off;
+    h->user_st = static_cast<hipStream_t>(stream);
+    h->st = h->user_st;
+    if (lambda_inst) h->lam_given.assign(lambda_inst, lambda_inst + L.n_inst);
 
     // ---- host preprocessing
-    // Column renumbering by decreasing nonzero count: the most gathered entries of x_hat
-    // then share cache lines.  It permutes the variables only; every output is scattered
-    // back to the caller's order.
+    // Column renumbering by decreasing nonzero count (single LP): the most gathered entries
+    // of x_hat then share cache lines.  It permutes the variables only; every output is
+    // scattered back to the caller's order.
     std::vector<int32_t> order((size_t)n), colr;
     std::vector<double> valr, cr, lr, ur;
     for (int64_t j = 0; j < n; ++j) order[j] = (int32_t)j;
@@ -461,30 +572,54 @@ extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t 
     h->dr = sc.dr;
     h->dc.assign((size_t)n, 1.0);
     for (int64_t j = 0; j < n; ++j) h->dc[order[j]] = sc.dc[j];  // caller's column order
-    std::vector<double> bs((size_t)m), cs((size_t)n);
-    for (int64_t i = 0; i < m; ++i) bs[i] = sc.dr[i] * b[i];
-    for (int64_t j = 0; j < n; ++j) cs[j] = sc.dc[j] * c[j];
-    auto nrm = [](const double *v, int64_t k) {
-        double s = 0;
-        for (int64_t i = 0; i < k; ++i) s += v[i] * v[i];
-        return std::sqrt(s);
-    };
-    h->bnorm = nrm(b, m);
-    h->cnorm = nrm(c, n);
-    h->beta_b = o.normalize_bc ? nrm(bs.data(), m) + 1.0 : 1.0;
-    h->beta_c = o.normalize_bc ? nrm(cs.data(), n) + 1.0 : 1.0;
-    const double bb = h->beta_b, bc = h->beta_c;
-    for (auto &v : bs) v /= bb;
-    for (auto &v : cs) v /= bc;
-    h->bsnorm = nrm(bs.data(), m);
-    h->csnorm = nrm(cs.data(), n);
+
+    // instance of every row and column; per instance: beta_b = ||D_r b|| + 1,
+    // beta_c = ||D_c c|| + 1 (Section 4.1) and the norms the termination test divides by
+    std::vector<int32_t> inst_row((size_t)m), inst_col((size_t)n);
+    for (int bi = 0; bi < L.n_inst; ++bi) {
+        for (int64_t i = L.row_off[bi]; i < L.row_off[bi + 1]; ++i) inst_row[i] = bi;
+        for (int64_t j = L.col_off[bi]; j < L.col_off[bi + 1]; ++j) inst_col[j] = bi;
+    }
+    std::vector<std::array<double, 8>> cst(L.n_inst);
+    for (int bi = 0; bi < L.n_inst; ++bi) {
+        const int64_t r0 = L.row_off[bi], r1 = L.row_off[bi + 1];
+        const int64_t c0 = L.col_off[bi], c1 = L.col_off[bi + 1];
+        double sb = 0, scc = 0, sbo = 0, sco = 0;
+        for (int64_t i = r0; i < r1; ++i) {
+            const double v = sc.dr[i] * b[i];
+            sb += v * v;
+            sbo += b[i] * b[i];
+        }
+        for (int64_t j = c0; j < c1; ++j) {
+            const double v = sc.dc[j] * c[j];
+            scc += v * v;
+            sco += c[j] * c[j];
+        }
+        const double bb = o.normalize_bc ? std::sqrt(sb) + 1.0 : 1.0;
+        const double bc = o.normalize_bc ? std::sqrt(scc) + 1.0 : 1.0;
+        double sbn = 0, scn = 0;  // ||D_r b / beta_b||, ||D_c c / beta_c||
+        for (int64_t i = r0; i < r1; ++i) {
+            const double v = sc.dr[i] * b[i] / bb;
+            sbn += v * v;
+        }
+        for (int64_t j = c0; j < c1; ++j) {
+            const double v = sc.dc[j] * c[j] / bc;
+            scn += v * v;
+        }
+        cst[bi] = {bb, bc, std::sqrt(sbo), std::sqrt(sco), std::sqrt(sbn), std::sqrt(scn), 0.0, 0.0};
+    }
+    h->beta_b = cst[0][0];
+    h->beta_c = cst[0][1];
+    h->bnorm = cst[0][2];
+    h->cnorm = cst[0][3];
+    h->bsnorm = cst[0][4];
+    h->csnorm = cst[0][5];
 
     ScheduleParams spar{o.tile_nnz, o.tile_rows, o.short_max, o.split_len, o.chunk_nnz};
-    build_schedule(m, rowptr, spar, nullptr, h->A.host);
-    build_schedule(n, rpt.data(), spar, nullptr, h->T.host);
+    build_schedule(m, rowptr, spar, L.batched ? inst_row.data() : nullptr, h->A.host);
+    build_schedule(n, rpt.data(), spar, L.batched ? inst_col.data() : nullptr, h->T.host);
 
-    Plan p = bound_plan(m, n, nnz, o);
-    Plan need = p;
+    Plan need = bound_plan(m, n, nnz, o, L.n_inst, L.batched);
     need.itemsA = (int)h->A.host.items.size();
     need.itemsT = (int)h->T.host.items.size();
     need.splitA = (int)h->A.host.splits.size();
@@ -507,7 +642,22 @@ extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t 
     h->A.rows = (int)m;
     h->T.rows = (int)n;
 
-    rc = create_device(h, rowptr, colidx, val, b, c, l, u, rpt, cit, pos, sc, bs, cs, order);
+    if (L.batched) {
+        // batched work is ordered on a stream of the library's own (stream capture needs a
+        // stream other than the legacy default one); each entry point first waits for the
+        // caller's stream
+        if (h->user_st && hipStreamSynchronize(h->user_st) != hipSuccess) {
+            delete h;
+            return fail(nullptr, HPRLP_EHIP, "caller stream synchronisation failed");
+        }
+        if (hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) != hipSuccess) {
+            delete h;
+            return fail(nullptr, HPRLP_EHIP, "hipStreamCreateWithFlags failed");
+        }
+        h->own_stream = true;
+    }
+    rc = create_device(h, L, rowptr, colidx, val, b, c, l, u, rpt, cit, pos, sc, order,
+                       inst_row, inst_col, cst);
     if (rc) {
         g_create_error = h->err;
         hprlp_destroy(h);
@@ -516,6 +666,111 @@ extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t 
     *out = h;
     return HPRLP_OK;
 }
+
+int workspace_impl(int32_t n_inst, int64_t m, int64_t n, int64_t nnz, const hprlp_options *opt,
+                   size_t *bytes, bool batched);
+
+}  // namespace
+
+// ============================================================================ C ABI
+
+extern "C" void hprlp_default_options(hprlp_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->check_every = 150;
+    o->max_iter = 10000000;
+    o->time_limit = 0;
+    o->alpha1 = 0.2;
+    o->alpha2 = 0.6;
+    o->alpha3 = 0.2;
+    o->sigma0 = 1.0;
+    o->ruiz_iters = 10;
+    o->pock_chambolle = 1;
+    o->normalize_bc = 1;
+    o->power_max_iter = 5000;
+    o->power_tol = 1e-10;
+    o->lambda_override = 0;
+    o->use_halpern = 1;
+    o->use_restart = 1;
+    o->sigma_update = 1;
+    o->precision = HPRLP_FP64;
+    o->tol_switch = 1e-5;
+    o->stall_checks = 10;
+    o->reorder = 1;
+    o->profile = 0;
+    o->verbose = 0;
+    resolve_options(*o);
+}
+
+namespace {
+int workspace_impl(int32_t n_inst, int64_t m, int64_t n, int64_t nnz, const hprlp_options *opt,
+                   size_t *bytes, bool batched) {
+    hprlp_options o;
+    if (opt) o = *opt;
+    else hprlp_default_options(&o);
+    resolve_options(o);
+    if (!bytes) return fail(nullptr, HPRLP_EINVAL, "bytes is null");
+    if (n_inst < 1 || m < 1 || n < 1 || nnz < 1 || nnz >= (1LL << 31) || m >= (1LL << 31) ||
+        n >= (1LL << 31) || n_inst > m || n_inst > n)
+        return fail(nullptr, HPRLP_EDIM, "bad dimensions");
+    std::string err;
+    int rc = validate_options(o, err);
+    if (rc) return fail(nullptr, rc, err);
+    *bytes = plan_bytes(bound_plan(m, n, nnz, o, n_inst, batched));
+    return HPRLP_OK;
+}
+}  // namespace
+
+extern "C" int hprlp_workspace_bytes(int64_t m1, int64_t m2, int64_t n, int64_t nnz,
+                                     const hprlp_options *opt, size_t *bytes) {
+    if (m1 < 0 || m2 < 0) return fail(nullptr, HPRLP_EDIM, "bad dimensions");
+    return workspace_impl(1, m1 + m2, n, nnz, opt, bytes, false);
+}
+
+extern "C" int hprlp_workspace_bytes_batched(int32_t n_inst, int64_t m, int64_t n, int64_t nnz,
+                                             const hprlp_options *opt, size_t *bytes) {
+    return workspace_impl(n_inst, m, n, nnz, opt, bytes, true);
+}
+
+extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
+                            const int64_t *rowptr, const int32_t *colidx, const double *val,
+                            const double *b, const double *c, const double *l, const double *u,
+                            const hprlp_options *opt, void *d_workspace, size_t ws_bytes,
+                            void *stream) {
+    if (!out) return fail(nullptr, HPRLP_EINVAL, "out is null");
+    *out = nullptr;
+    if (m1 < 0 || m2 < 0 || m1 + m2 < 1 || n < 1)
+        return fail(nullptr, HPRLP_EDIM, "bad dimensions (need m1, m2 >= 0, m1 + m2 >= 1, n >= 1)");
+    Layout L{1, {0, m1 + m2}, {0, n}, {m1}, false};
+    return create_impl(out, L, rowptr, colidx, val, b, c, l, u, nullptr, opt, d_workspace,
+                       ws_bytes, stream);
+}
+
+extern "C" int hprlp_create_batched(hprlp_handle **out, int32_t n_inst,
+                                    const int64_t *inst_row_off, const int64_t *inst_col_off,
+                                    const int64_t *inst_m1, const int64_t *rowptr,
+                                    const int32_t *colidx, const double *val, const double *b,
+                                    const double *c, const double *l, const double *u,
+                                    const double *lambda_inst, const hprlp_options *opt,
+                                    void *d_workspace, size_t ws_bytes, void *stream) {
+    if (!out || !inst_row_off || !inst_col_off || !inst_m1)
+        return fail(nullptr, HPRLP_EINVAL, "null argument");
+    *out = nullptr;
+    if (n_inst < 1) return fail(nullptr, HPRLP_EDIM, "n_inst must be >= 1");
+    Layout L;
+    L.n_inst = n_inst;
+    L.batched = true;
+    L.row_off.assign(inst_row_off, inst_row_off + n_inst + 1);
+    L.col_off.assign(inst_col_off, inst_col_off + n_inst + 1);
+    L.m1.assign(inst_m1, inst_m1 + n_inst);
+    if (L.row_off[n_inst] < 1 || L.col_off[n_inst] < 1 || L.row_off[n_inst] >= (1LL << 31) ||
+        L.col_off[n_inst] >= (1LL << 31))
+        return fail(nullptr, HPRLP_EDIM, "bad dimensions");
+    return create_impl(out, L, rowptr, colidx, val, b, c, l, u, lambda_inst, opt, d_workspace,
+                       ws_bytes, stream);
+}
+
 namespace {
 
 // Halpern weights of Algorithm 2 at inner counter t (before it is incremented).
@@ -536,6 +791,20 @@ void fill_scalars(const hprlp_handle *h, IterScalars &s) {
 
 const void *cur_set(const hprlp_handle *h) {
     return h->prec == 1 ? static_cast<const void *>(&h->v32) : static_cast<const void *>(&h->v64);
+}
+
+BatchArgs batch_args(const hprlp_handle *h, int iter_off) {
+    BatchArgs a;
+    a.sigma = h->bd.sigma;
+    a.lam = h->bd.lam;
+    a.kstart = h->bd.kstart;
+    a.kbase = h->bd.kbase;
+    a.m1_end = h->bd.m1_end;
+    a.active = h->bd.active;
+    a.inv_norm = h->bd.inv_norm;
+    a.iter_off = iter_off;
+    a.halpern = h->opt.use_halpern;
+    return a;
 }
 
 struct ProfRec {
@@ -587,46 +856,61 @@ double merit_of(const double *q, double sigma, double lambda) {
     return std::sqrt(v > 0.0 ? v : 0.0);
 }
 
-int power_method(hprlp_handle *h, int *iters) {
+// Power method (Section 4.1) on every instance at once: v0 = 1/sqrt(m_b) on the rows of
+// instance b; lambda_b is the Rayleigh quotient at the first iteration whose change is
+// <= power_tol relative (or at power_max_iter).  Writes lam[b] and the largest iteration
+// count over the instances.
+int power_method(hprlp_handle *h, std::vector<double> &lam, int *iters) {
     const int64_t m = h->m;
-    std::vector<double> v0((size_t)m, 1.0 / std::sqrt((double)m));
-    if (h->mixed)
-        for (int64_t i = 0; i < m; ++i) v0[i] *= h->dr[i];
+    const int ni = h->n_inst;
+    const std::vector<int64_t> &roff = h->row_off;
+    std::vector<double> v0((size_t)m);
+    for (int b = 0; b < ni; ++b)
+        for (int64_t i = roff[b]; i < roff[b + 1]; ++i)
+            v0[i] = (1.0 / std::sqrt((double)(roff[b + 1] - roff[b]))) *
+                    (h->mixed ? h->dr[i] : 1.0);
     int rc = upload(h, h->vg, v0.data(), (size_t)m);
     if (rc) return rc;
-    const double one = 1.0;
-    HIPCHK(h, hipMemcpyAsync(h->inv_norm, &one, sizeof(double), hipMemcpyHostToDevice, h->st));
-    HIPCHK(h, hipStreamSynchronize(h->st));
+    std::vector<double> ones((size_t)ni, 1.0);
+    if ((rc = upload(h, h->inv_norm, ones.data(), (size_t)ni))) return rc;
+    const BatchArgs ba = batch_args(h, 0);
     const int maxit = h->opt.power_max_iter;
     const double tol = h->opt.power_tol;
-    double rq_prev = 0.0, lam = 0.0;
-    int done_it = 0;
+    std::vector<double> rq_prev((size_t)ni, 0.0);
+    std::vector<int> done((size_t)ni, 0);
+    lam.assign((size_t)ni, 0.0);
+    int n_done = 0, max_it = 0;
     const int B = 32;
-    for (int k0 = 0; k0 < maxit && !done_it; k0 += B) {
+    for (int k0 = 0; k0 < maxit && n_done < ni; k0 += B) {
         const int kb = std::min(B, maxit - k0);
         for (int kk = 0; kk < kb; ++kk) {
-            hipError_t e = launch_power_iter(h->mixed, h->mixed, h->A, h->T, h->vg, h->w,
-                                             h->v64.sc, h->v64.sr, h->inv_norm, h->partsT,
-                                             h->partsA, h->hist, k0 + kk, h->st);
+            hipError_t e = launch_power_iter(
+                h->mixed, h->mixed, h->A, h->T, h->vg, h->w, h->v64.sc, h->v64.sr, h->inv_norm,
+                h->partsT, h->partsA, h->hist, k0 + kk, h->st, h->batched ? &ba : nullptr,
+                h->batched ? &h->segA : nullptr, h->batched ? &h->segT : nullptr,
+                h->batched ? h->bd.seg_tmp : nullptr);
             if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("power launch: ") + hipGetErrorString(e));
         }
-        HIPCHK(h, hipMemcpyAsync(h->pinned, h->hist + k0, kb * sizeof(double),
-                                 hipMemcpyDeviceToHost, h->st));
-        HIPCHK(h, hipStreamSynchronize(h->st));
-        for (int kk = 0; kk < kb; ++kk) {
-            const int it = k0 + kk + 1;
-            const double rq = h->pinned[kk];
-            lam = rq;
-            if (it > 1 && std::fabs(rq - rq_prev) <= tol * rq) {
-                done_it = it;
-                break;
+        if ((rc = download(h, h->pinned, h->hist + (size_t)k0 * ni, (size_t)kb * ni))) return rc;
+        for (int b = 0; b < ni; ++b) {
+            if (done[b]) continue;
+            for (int kk = 0; kk < kb; ++kk) {
+                const int it = k0 + kk + 1;
+                const double rq = h->pinned[(size_t)kk * ni + b];
+                lam[b] = rq;
+                if ((it > 1 && std::fabs(rq - rq_prev[b]) <= tol * rq) || it == maxit) {
+                    done[b] = it;
+                    break;
+                }
+                rq_prev[b] = rq;
             }
-            rq_prev = rq;
-            if (it == maxit) done_it = it;
+            if (done[b]) {
+                n_done++;
+                max_it = std::max(max_it, done[b]);
+            }
         }
     }
-    *iters = done_it;
-    h->lambda = lam;
+    *iters = max_it;
     return HPRLP_OK;
 }
 
@@ -696,10 +980,34 @@ int copy_out(hprlp_handle *h, double *dst, const double *src, long long k) {
     return HPRLP_OK;
 }
 
-}  // namespace
+// w_bar of the last check, original space, into x, y, z (host or device pointers).
+int write_outputs(hprlp_handle *h, double *x, double *y, double *z) {
+    const bool f32 = h->prec == 1;
+    const void *xb = f32 ? (const void *)h->v32.xbar : (const void *)h->v64.xbar;
+    const void *yb = f32 ? (const void *)h->v32.ybar : (const void *)h->v64.ybar;
+    const void *zb = f32 ? (const void *)h->v32.zint : (const void *)h->v64.zint;
+    double *ox = h->outv, *oy = h->outv + h->n, *oz = h->outv + h->n + h->m;
+    hipError_t e = launch_scale_out(ox, xb, f32, h->ux, 0.0, h->cperm, h->n, h->st);
+    if (e == hipSuccess) e = launch_scale_out(oy, yb, f32, h->uy, 0.0, nullptr, h->m, h->st);
+    if (e == hipSuccess) e = launch_scale_out(oz, zb, f32, h->chk.co, 0.0, h->cperm, h->n, h->st);
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    int rc;
+    if ((rc = copy_out(h, x, ox, h->n)) || (rc = copy_out(h, y, oy, h->m)) ||
+        (rc = copy_out(h, z, oz, h->n)))
+        return rc;
+    return HPRLP_OK;
+}
 
-extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int *status) {
-    if (!h) return fail(nullptr, HPRLP_EINVAL, "null handle");
+double bytes_per_iter(const hprlp_handle *h) {
+    const double sv = h->mixed ? 4.0 : 8.0, svec = (h->prec == 1) ? 4.0 : 8.0;
+    return 2.0 * h->nnz * (sv + 4.0) + 4.0 * (h->m + h->n + 2) + 7.0 * h->n * svec +
+           5.0 * h->m * svec;
+}
+
+// ---------------------------------------------------------------------------- one LP
+
+int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) {
     const hprlp_options &o = h->opt;
     HIPCHK(h, hipStreamSynchronize(h->st));
     const double t_start = now_ms();
@@ -712,8 +1020,10 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     int piters = 0;
     if (o.lambda_override > 0) {
         h->lambda = o.lambda_override;
-    } else if ((rc = power_method(h, &piters))) {
-        return rc;
+    } else {
+        std::vector<double> lam;
+        if ((rc = power_method(h, lam, &piters))) return rc;
+        h->lambda = lam[0];
     }
     const double t_power = now_ms() - t_start;
     if (!(h->lambda > 0.0) || !std::isfinite(h->lambda)) {
@@ -812,7 +1122,7 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
             h->trace.push_back(row);
             break;
         }
-        // ---- restart criteria (Section 3.1), with the reading documented in DESIGN notes
+        // ---- restart criteria (Section 3.1)
         bool restart = false;
         if (o.use_restart) {
             if (merit <= o.alpha1 * merit0) restart = true;
@@ -858,21 +1168,8 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     }
     HIPCHK(h, hipStreamSynchronize(h->st));
     if (pp && (rc = flush_prof())) return rc;
-    // ---- outputs: w_bar of the last check, original space
-    const bool f32 = h->prec == 1;
-    const void *xb = f32 ? (const void *)h->v32.xbar : (const void *)h->v64.xbar;
-    const void *yb = f32 ? (const void *)h->v32.ybar : (const void *)h->v64.ybar;
-    const void *zb = f32 ? (const void *)h->v32.zint : (const void *)h->v64.zint;
-    double *ox = h->outv, *oy = h->outv + h->n, *oz = h->outv + h->n + h->m;
-    hipError_t e = launch_scale_out(ox, xb, f32, h->ux, 0.0, h->cperm, h->n, h->st);
-    if (e == hipSuccess) e = launch_scale_out(oy, yb, f32, h->uy, 0.0, nullptr, h->m, h->st);
-    if (e == hipSuccess) e = launch_scale_out(oz, zb, f32, h->chk.co, 0.0, h->cperm, h->n, h->st);
-    if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
-    HIPCHK(h, hipStreamSynchronize(h->st));
     const double t_end = now_ms();
-    if ((rc = copy_out(h, x, ox, h->n)) || (rc = copy_out(h, y, oy, h->m)) ||
-        (rc = copy_out(h, z, oz, h->n)))
-        return rc;
+    if ((rc = write_outputs(h, x, y, z))) return rc;
     h->solved = true;
     hprlp_stats_t &s = h->stats;
     s.iters = h->k;
@@ -886,9 +1183,7 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     s.beta_c = h->beta_c;
     s.t_power_ms = t_power;
     s.t_solve_ms = t_end - t_start;
-    const double sv = h->mixed ? 4.0 : 8.0, svec = (h->prec == 1) ? 4.0 : 8.0;
-    s.bytes_per_iter = 2.0 * h->nnz * (sv + 4.0) + 4.0 * (h->m + h->n + 2) + 7.0 * h->n * svec +
-                       5.0 * h->m * svec;
+    s.bytes_per_iter = bytes_per_iter(h);
     s.col_pass_ms = prof_ms[0];
     s.row_pass_ms = prof_ms[1];
     s.col_pass_launches = prof_n[0];
@@ -899,9 +1194,230 @@ extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int
     return HPRLP_OK;
 }
 
+// ---------------------------------------------------------------------------- a batch
+
+// Record one chunk of check_every iterations on the library stream: first iteration (keep)
+// + its check sums, plain iterations, last iteration (keep) + check sums, the decisions of
+// every instance, the restart copies, and the iteration counter advance.
+int record_chunk(hprlp_handle *h, int prec) {
+    const int L = (int)h->opt.check_every;
+    const void *vs = prec == 1 ? static_cast<const void *>(&h->v32)
+                               : static_cast<const void *>(&h->v64);
+    const IterScalars unused{};  // batched passes read their scalars from device memory
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < L && e == hipSuccess; ++i) {
+        const bool keep = (i == 0 || i == L - 1);
+        const BatchArgs ba = batch_args(h, i);
+        e = launch_col_pass(prec, keep, h->T, vs, unused, h->st, nullptr, &ba);
+        if (e == hipSuccess) e = launch_row_pass(prec, keep, h->A, vs, unused, h->st, nullptr, &ba);
+        if (e == hipSuccess && keep) {
+            double *res = i == 0 ? h->bd.res_first : h->bd.res_chk;
+            e = launch_check_row(prec, h->A, vs, h->chk, h->v64.bd, 0, h->partsA, res, h->st,
+                                 &ba, &h->segA, 2 * kNQ);
+            if (e == hipSuccess)
+                e = launch_check_col(prec, h->T, vs, h->chk, h->v64.cd, h->v64.sc, h->partsT,
+                                     res + kNQ, h->st, &ba, &h->segT, 2 * kNQ);
+        }
+    }
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("chunk launch: ") + hipGetErrorString(e));
+    const hprlp_options &o = h->opt;
+    DecideArgs d;
+    d.n_inst = h->n_inst; d.chunk = L; d.max_iter = o.max_iter;
+    d.tol = o.tol; d.alpha1 = o.alpha1; d.alpha2 = o.alpha2; d.alpha3 = o.alpha3;
+    d.tol_switch = o.tol_switch; d.use_restart = o.use_restart; d.sigma_update = o.sigma_update;
+    d.res_first = h->bd.res_first; d.res_chk = h->bd.res_chk; d.cst = h->bd.cst;
+    d.sigma = h->bd.sigma; d.lam = h->bd.lam; d.merit0 = h->bd.merit0;
+    d.merit_prev = h->bd.merit_prev; d.kstart = h->bd.kstart; d.kbase = h->bd.kbase;
+    d.iters_done = h->bd.iters_done; d.restarts = h->bd.restarts; d.nchecks = h->bd.nchecks;
+    d.active = h->bd.active; d.status = h->bd.status; d.restart_flag = h->bd.restart_flag;
+    d.last = h->bd.last; d.trace = h->bd.trace; d.summary = h->bd.summary;
+    e = launch_decide(d, h->st);
+    if (e == hipSuccess)
+        e = launch_restart_batched(prec == 1, vs, h->bd.row_off, h->bd.col_off,
+                                   h->bd.restart_flag, h->n_inst, h->st);
+    if (e == hipSuccess) e = launch_advance(h->bd.kbase, L, h->st);
+    if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("chunk launch: ") + hipGetErrorString(e));
+    return HPRLP_OK;
+}
+
+// The chunk graph of one precision phase, captured on first use and kept with the handle.
+int get_graph(hprlp_handle *h, int prec, hipGraphExec_t *out) {
+    if (!h->graphs[prec]) {
+        HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+        const int rc = record_chunk(h, prec);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) return fail(h, HPRLP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+        h->graphs[prec] = ex;
+    }
+    *out = h->graphs[prec];
+    return HPRLP_OK;
+}
+
+int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status) {
+    const hprlp_options &o = h->opt;
+    const int ni = h->n_inst;
+    if (h->user_st) HIPCHK(h, hipStreamSynchronize(h->user_st));
+    const double t_start = now_ms();
+    h->stats = hprlp_stats_t{};
+    h->inst_stats.clear();
+    h->prec = h->f32phase ? 1 : (h->mixed ? 2 : 0);
+    int rc;
+    // every instance iterates from w = 0 with sigma = sigma0; outer loops start at k = 0
+    {
+        std::vector<double> sig((size_t)ni, o.sigma0), zeros((size_t)ni, 0.0);
+        std::vector<long long> zl((size_t)ni, 0);
+        std::vector<int> ones((size_t)ni, 1), zi((size_t)ni, 0);
+        const long long kb0 = 0;
+        if ((rc = upload(h, h->bd.sigma, sig.data(), sig.size())) ||
+            (rc = upload(h, h->bd.lam, zeros.data(), zeros.size())) ||
+            (rc = upload(h, h->bd.merit0, zeros.data(), zeros.size())) ||
+            (rc = upload(h, h->bd.merit_prev, zeros.data(), zeros.size())) ||
+            (rc = upload(h, h->bd.kstart, zl.data(), zl.size())) ||
+            (rc = upload(h, h->bd.kbase, &kb0, 1)) ||
+            (rc = upload(h, h->bd.iters_done, zl.data(), zl.size())) ||
+            (rc = upload(h, h->bd.restarts, zl.data(), zl.size())) ||
+            (rc = upload(h, h->bd.nchecks, zl.data(), zl.size())) ||
+            (rc = upload(h, h->bd.active, ones.data(), ones.size())) ||
+            (rc = upload(h, h->bd.status, zi.data(), zi.size())) ||
+            (rc = upload(h, h->bd.restart_flag, zi.data(), zi.size())))
+            return rc;
+    }
+    std::vector<double> lam((size_t)ni, o.lambda_override);
+    int piters = 0;
+    if (!h->lam_given.empty()) lam = h->lam_given;
+    else if (!(o.lambda_override > 0) && (rc = power_method(h, lam, &piters))) return rc;
+    for (int b = 0; b < ni; ++b)
+        if (!(lam[b] > 0.0) || !std::isfinite(lam[b])) {
+            h->stats.status = HPRLP_NUMERICAL;
+            if (status) *status = HPRLP_NUMERICAL;
+            return fail(h, HPRLP_OK, "power method gave lambda <= 0 for instance " + std::to_string(b));
+        }
+    if ((rc = upload(h, h->bd.lam, lam.data(), lam.size()))) return rc;
+    const double t_power = now_ms() - t_start;
+    if ((rc = zero_state(h))) return rc;
+
+    std::vector<double> kkt_hist;
+    long long k = 0, iters_fp32 = 0;
+    int st_all = HPRLP_UNSOLVED;
+    for (;;) {
+        hipGraphExec_t ex;
+        if ((rc = get_graph(h, h->prec, &ex))) return rc;
+        HIPCHK(h, hipGraphLaunch(ex, h->st));
+        if ((rc = download(h, h->pinned, h->bd.summary, 4))) return rc;
+        const double n_active = h->pinned[0], max_kkt = h->pinned[1], n_above = h->pinned[2];
+        k = (long long)h->pinned[3];
+        if (h->prec == 1) iters_fp32 = k;
+        if (o.verbose)
+            std::fprintf(stderr, "hprlp batch k=%lld active=%.0f max_kkt=%.2e\n", k, n_active, max_kkt);
+        if (n_active == 0) break;
+        if (k >= o.max_iter) {
+            st_all = HPRLP_ITER_LIMIT;
+            break;
+        }
+        if (o.time_limit > 0 && (now_ms() - t_start) / 1000.0 >= o.time_limit) {
+            st_all = HPRLP_TIME_LIMIT;
+            break;
+        }
+        if (h->prec == 1) {
+            // as for one LP, on the largest rel. KKT over the instances still iterating
+            bool sw = n_above == 0;
+            kkt_hist.push_back(max_kkt);
+            const size_t S = (size_t)o.stall_checks, H = kkt_hist.size();
+            if (!sw && S > 0 && H > S) {
+                const double before = *std::min_element(kkt_hist.begin(), kkt_hist.end() - S);
+                const double recent = *std::min_element(kkt_hist.end() - S, kkt_hist.end());
+                sw = recent > 0.5 * before;
+            }
+            if (sw && (rc = promote(h))) return rc;
+        }
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const double t_end = now_ms();
+    if ((rc = write_outputs(h, x, y, z))) return rc;
+    // per-instance results
+    std::vector<int> ist((size_t)ni);
+    std::vector<long long> idone((size_t)ni), irest((size_t)ni), inch((size_t)ni);
+    std::vector<double> isig((size_t)ni), ilast((size_t)ni * 6);
+    if ((rc = download(h, ist.data(), h->bd.status, ist.size())) ||
+        (rc = download(h, idone.data(), h->bd.iters_done, idone.size())) ||
+        (rc = download(h, irest.data(), h->bd.restarts, irest.size())) ||
+        (rc = download(h, inch.data(), h->bd.nchecks, inch.size())) ||
+        (rc = download(h, isig.data(), h->bd.sigma, isig.size())) ||
+        (rc = download(h, ilast.data(), h->bd.last, ilast.size())))
+        return rc;
+    h->inst_stats.assign((size_t)ni, hprlp_stats_t{});
+    std::vector<double> cst((size_t)ni * 8);
+    if ((rc = download(h, cst.data(), h->bd.cst, cst.size()))) return rc;
+    hprlp_stats_t &s = h->stats;
+    int worst = HPRLP_OPTIMAL;
+    for (int b = 0; b < ni; ++b) {
+        hprlp_stats_t &q = h->inst_stats[b];
+        q.status = ist[b] ? ist[b] : st_all;
+        q.iters = ist[b] ? idone[b] : k;
+        q.restarts = irest[b];
+        q.sigma = isig[b];
+        q.lambda = lam[b];
+        q.power_iters = piters;
+        q.rel_p = ilast[b * 6 + 0]; q.rel_d = ilast[b * 6 + 1]; q.rel_gap = ilast[b * 6 + 2];
+        q.pobj = ilast[b * 6 + 3]; q.dobj = ilast[b * 6 + 4];
+        q.beta_b = cst[(size_t)b * 8 + 0];
+        q.beta_c = cst[(size_t)b * 8 + 1];
+        q.t_solve_ms = t_end - t_start;
+        q.t_power_ms = t_power;
+        q.n_checks = inch[b];
+        if (q.status != HPRLP_OPTIMAL && worst == HPRLP_OPTIMAL) worst = q.status;
+        s.restarts += q.restarts;
+        s.rel_p = std::max(s.rel_p, q.rel_p);
+        s.rel_d = std::max(s.rel_d, q.rel_d);
+        s.rel_gap = std::max(s.rel_gap, q.rel_gap);
+        s.pobj += q.pobj;
+        s.dobj += q.dobj;
+    }
+    h->solved = true;
+    s.iters = k;
+    s.iters_fp32 = h->f32phase ? iters_fp32 : 0;
+    s.status = worst;
+    s.power_iters = piters;
+    s.t_power_ms = t_power;
+    s.t_solve_ms = t_end - t_start;
+    s.bytes_per_iter = bytes_per_iter(h);
+    s.n_checks = k / o.check_every;
+    if (status) *status = worst;
+    return HPRLP_OK;
+}
+
+}  // namespace
+
+extern "C" int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int *status) {
+    if (!h) return fail(nullptr, HPRLP_EINVAL, "null handle");
+    return h->batched ? solve_batched(h, x, y, z, status) : solve_single(h, x, y, z, status);
+}
+
 extern "C" int hprlp_stats(const hprlp_handle *h, hprlp_stats_t *out) {
     if (!h || !out) return fail(const_cast<hprlp_handle *>(h), HPRLP_EINVAL, "null argument");
     *out = h->stats;
+    return HPRLP_OK;
+}
+
+extern "C" int hprlp_stats_instance(const hprlp_handle *hc, int32_t i, hprlp_stats_t *out) {
+    hprlp_handle *h = const_cast<hprlp_handle *>(hc);
+    if (!h || !out) return fail(h, HPRLP_EINVAL, "null argument");
+    if (i < 0 || i >= h->n_inst) return fail(h, HPRLP_EINVAL, "instance index out of range");
+    if (!h->batched) {
+        *out = h->stats;
+        return HPRLP_OK;
+    }
+    if (h->inst_stats.empty()) return fail(h, HPRLP_ESTATE, "no solve has run yet");
+    *out = h->inst_stats[i];
     return HPRLP_OK;
 }
 
@@ -914,6 +1430,8 @@ extern "C" int hprlp_get_iterate(const hprlp_handle *hc, int which, double *out)
         return HPRLP_OK;
     }
     if (!h->solved) return fail(h, HPRLP_ESTATE, "no solve has run yet");
+    if (h->batched && which == HPRLP_XCUR)
+        return fail(h, HPRLP_EINVAL, "XCUR needs one inner counter; a batch has one per instance");
     const bool f32 = h->prec == 1;
     double *tmp = h->outv;
     hipError_t e = hipSuccess;
@@ -962,12 +1480,37 @@ extern "C" int hprlp_get_trace(const hprlp_handle *hc, double *out, long long ca
     return HPRLP_OK;
 }
 
+extern "C" int hprlp_get_trace_instance(const hprlp_handle *hc, int32_t i, double *out,
+                                        long long cap, long long *n_rows) {
+    hprlp_handle *h = const_cast<hprlp_handle *>(hc);
+    if (!h || !n_rows) return fail(h, HPRLP_EINVAL, "null argument");
+    if (!h->batched) return fail(h, HPRLP_EINVAL, "not a batched handle");
+    if (i < 0 || i >= h->n_inst) return fail(h, HPRLP_EINVAL, "instance index out of range");
+    if (!h->solved) return fail(h, HPRLP_ESTATE, "no solve has run yet");
+    long long nc = 0;
+    int rc = download(h, &nc, h->bd.nchecks + i, 1);
+    if (rc) return rc;
+    *n_rows = std::min<long long>(nc, kTraceRows);
+    const long long k = std::min<long long>(cap, *n_rows);
+    if (out && k > 0)
+        rc = download(h, out, h->bd.trace + (size_t)i * kTraceRows * kTraceCols,
+                      (size_t)k * kTraceCols);
+    return rc;
+}
+
 extern "C" int hprlp_time_passes(hprlp_handle *h, int reps, double *col_ms, double *row_ms) {
     if (!h || reps < 1) return fail(h, HPRLP_EINVAL, "bad argument");
     if (!h->solved) return fail(h, HPRLP_ESTATE, "call after a solve");
     IterScalars s;
     fill_scalars(h, s);
     const void *vs = cur_set(h);
+    const BatchArgs ba = batch_args(h, 0);
+    const BatchArgs *pba = h->batched ? &ba : nullptr;
+    if (h->batched) {  // time every instance's work, whatever the last solve left active
+        std::vector<int> ones((size_t)h->n_inst, 1);
+        int rc = upload(h, h->bd.active, ones.data(), ones.size());
+        if (rc) return rc;
+    }
     hipEvent_t e[4];
     for (int i = 0; i < 4; ++i) {
         e[i] = pool_event(h, i);
@@ -975,13 +1518,13 @@ extern "C" int hprlp_time_passes(hprlp_handle *h, int reps, double *col_ms, doub
     }
     HIPCHK(h, hipEventRecord(e[0], h->st));
     for (int i = 0; i < reps; ++i) {
-        hipError_t r = launch_col_pass(h->prec, false, h->T, vs, s, h->st);
+        hipError_t r = launch_col_pass(h->prec, false, h->T, vs, s, h->st, nullptr, pba);
         if (r != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(r));
     }
     HIPCHK(h, hipEventRecord(e[1], h->st));
     HIPCHK(h, hipEventRecord(e[2], h->st));
     for (int i = 0; i < reps; ++i) {
-        hipError_t r = launch_row_pass(h->prec, false, h->A, vs, s, h->st);
+        hipError_t r = launch_row_pass(h->prec, false, h->A, vs, s, h->st, nullptr, pba);
         if (r != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(r));
     }
     HIPCHK(h, hipEventRecord(e[3], h->st));
@@ -1000,7 +1543,10 @@ extern "C" const char *hprlp_last_error(const hprlp_handle *h) {
 
 extern "C" void hprlp_destroy(hprlp_handle *h) {
     if (!h) return;
+    for (hipGraphExec_t g : h->graphs)
+        if (g) (void)hipGraphExecDestroy(g);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
     delete h;
 }

@@ -25,7 +25,7 @@ constexpr int kMaxTileRows = 1024;// kWG threads x 4 rows (kernels.hip, kRPT)
 //   TILE : {r0, P0, inst, nrows << 14 | cnt << 2 | IT_TILE}  rows [r0, r0+nrows), all short,
 //          nonzeros [P0, P0+cnt) with cnt <= tile_nnz <= 2048, nrows <= tile_rows <= 1024
 //   ROW  : {r, P0, P1, inst << 2 | IT_ROW}     one long row, whole workgroup
-//   CHUNK: {p0, p1, slot, IT_CHUNK}            piece of a split row; partial -> split_part[slot]
+//   CHUNK: {p0, p1, inst, slot << 2 | IT_CHUNK} piece of a split row; partial -> split_part[slot]
 //   EMPTY: {0, 0, 0, IT_EMPTY}                 padding so each class starts on an XCD boundary
 // splits: {row, slot0, nslots, inst} finished (fixed-order sum + epilogue) by a second kernel.
 struct Schedule {
@@ -79,6 +79,21 @@ struct IterScalars {
     long long m1;       // first inequality row (single LP)
 };
 
+// Per-instance scalars of a batched solve, read by the passes on the device (one set per
+// block-diagonal instance; the work items of one instance never mix with another's).
+//   t_b = (*kbase + iter_off) - kstart[b] is the inner counter of instance b at this
+//   iteration (kbase: iterations completed before the current chunk; iter_off: position of
+//   the iteration inside the chunk, fixed when the chunk is captured).
+struct BatchArgs {
+    const double *sigma = nullptr, *lam = nullptr;
+    const long long *kstart = nullptr, *kbase = nullptr;
+    const int *m1_end = nullptr;   // absolute index of the instance's first inequality row
+    const int *active = nullptr;   // 0 once the instance has stopped
+    const double *inv_norm = nullptr;  // power method normalisation per instance
+    int iter_off = 0;
+    int halpern = 1;
+};
+
 // Check-pass multipliers (always FP64).
 struct CheckData {
     double *ro = nullptr, *rs = nullptr, *ys = nullptr;  // per row
@@ -89,24 +104,65 @@ struct CheckData {
 // ---------------------------------------------------------------- kernel launchers
 // prec: 0 = FP64 (double A, double vectors, no fold); 1 = MIXED FP32 phase (float A, float
 // vectors, fold); 2 = MIXED FP64 phase (float A, double vectors, fold).
-// ev_mid (nullable): recorded between the main SpMV kernel and the split-row finisher
+// ev_mid (nullable): recorded between the main SpMV kernel and the split-row finisher.
+// ba (nullable): batched solve, scalars per instance from device memory instead of s.
 hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vecset,
-                           const IterScalars &s, hipStream_t st, hipEvent_t ev_mid = nullptr);
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev_mid = nullptr,
+                           const BatchArgs *ba = nullptr);
 hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vecset,
-                           const IterScalars &s, hipStream_t st, hipEvent_t ev_mid = nullptr);
-// check passes: write kNQ partial sums per slot into parts, then reduce into out[kNQ]
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev_mid = nullptr,
+                           const BatchArgs *ba = nullptr);
+// Check passes: write kNQ partial sums per workgroup slot into parts; then either reduce all
+// slots into out[kNQ] (single LP, seg == nullptr) or, per instance b, the slots listed in
+// seg->slots[seg->ptr[b] .. seg->ptr[b+1]) into out[b * out_stride + j].
 // bd64 / cd64 / sc64: FP64 right-hand side, cost and folded column scaling (dc^2, MIXED only)
+struct Segments {
+    const int *ptr = nullptr;    // [n_inst + 1]
+    const int *slots = nullptr;  // slot indices grouped by instance, in slot order
+    int n_inst = 0;
+};
 hipError_t launch_check_row(int prec, const DevMat &A, const void *vecset, const CheckData &cd,
                             const double *bd64, long long m1, double *parts, double *out,
-                            hipStream_t st);
+                            hipStream_t st, const BatchArgs *ba = nullptr,
+                            const Segments *seg = nullptr, int out_stride = 0);
 hipError_t launch_check_col(int prec, const DevMat &T, const void *vecset, const CheckData &cd,
                             const double *cd64, const double *sc64, double *parts, double *out,
-                            hipStream_t st);
-// power method iteration k (0-based): hist[k] = Rayleigh quotient, inv_norm updated
+                            hipStream_t st, const BatchArgs *ba = nullptr,
+                            const Segments *seg = nullptr, int out_stride = 0);
+// power method iteration k (0-based): hist[k] = Rayleigh quotient, inv_norm updated.
+// Batched: hist[k * n_inst + b] and inv_norm[b] per instance (segA/segT: slot lists of A, A^T).
 hipError_t launch_power_iter(bool mat_f32, bool fold, const DevMat &A, const DevMat &T,
                              double *vg, double *w, const double *sc, const double *sr,
                              double *inv_norm, double *parts_c, double *parts_r, double *hist,
-                             int k, hipStream_t st);
+                             int k, hipStream_t st, const BatchArgs *ba = nullptr,
+                             const Segments *segA = nullptr, const Segments *segT = nullptr,
+                             double *seg_tmp = nullptr);
+
+// Batched decisions (restart criteria, SigmaUpdate, termination) for every instance after a
+// chunk of `chunk` iterations; see kernels.hip k_decide for the layout of `dec`.
+struct DecideArgs {
+    int n_inst, chunk;
+    long long max_iter;
+    double tol, alpha1, alpha2, alpha3, tol_switch;
+    int use_restart, sigma_update;
+    const double *res_first;  // [n_inst][2][kNQ] sums of the chunk's first iteration
+    const double *res_chk;    // [n_inst][2][kNQ] sums of the chunk's last iteration
+    const double *cst;        // [n_inst][8]: beta_b, beta_c, ||b||, ||c||, ||b~||, ||c~||
+    double *sigma, *lam, *merit0, *merit_prev;
+    long long *kstart, *kbase, *iters_done, *restarts, *nchecks;
+    int *active, *status, *restart_flag;
+    double *last;             // [n_inst][6]: rel_p, rel_d, rel_gap, pobj, dobj, merit
+    double *trace;            // [n_inst][kTraceRows][kTraceCols]
+    double *summary;          // [4]: active count, max rel. KKT of active instances, ...
+};
+constexpr int kTraceRows = 64;
+constexpr int kTraceCols = 10;
+hipError_t launch_decide(const DecideArgs &d, hipStream_t st);
+// w^{r+1,0} = w_bar for the instances flagged by restart_flag (precision V of the set)
+hipError_t launch_restart_batched(bool f32, const void *vecset, const int *row_off,
+                                  const int *col_off, const int *restart_flag, int n_inst,
+                                  hipStream_t st);
+hipError_t launch_advance(long long *kbase, int chunk, hipStream_t st);
 // vector utilities
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t st);
 hipError_t launch_fill_f(float *p, long long n, float v, hipStream_t st);

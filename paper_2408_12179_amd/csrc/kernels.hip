@@ -21,7 +21,12 @@
 // cache lines stay on one XCD's L2) while all XCDs see the same mix of heavy and light work.
 // Check passes (every check_every iterations) reuse the same kernel with epilogues that
 // produce per-workgroup partial sums of the termination / restart / sigma quantities,
-// reduced by a single-workgroup kernel in a fixed order.
+// reduced in a fixed order (one workgroup for a single LP, one per instance for a batch).
+//
+// Batched solves (many LPs packed block-diagonally) run the same passes; each work item
+// belongs to one instance, and its scalars (sigma, lambda, the Halpern counter, the first
+// inequality row, whether it still iterates) come from per-instance device arrays, so a
+// whole chunk of iterations can be captured once in a hipGraph.
 #include "hprlp_internal.h"
 
 namespace hprlp {
@@ -70,13 +75,54 @@ template <class V> __device__ __forceinline__ V clampv(V v, V lo, V hi) {
 template <class M, class V> struct AccT { using type = double; };
 template <> struct AccT<float, float> { using type = float; };
 
+// Scalars one work item needs: from kernel arguments (single LP) or from the per-instance
+// arrays of a batched solve.  Halpern weights of Algorithm 2 at inner counter t:
+// x^{r,t} = x0/(t+1) + t/(t+1) x_hat, y^{r,t+1} = y0/(t+2) + (t+1)/(t+2) y_hat.
+struct PassCtx {
+    double sigma, lam_sigma, hx0, hx1, hy0, hy1, inv_norm;
+    long long m1_end;
+    int active;
+};
+
+__device__ __forceinline__ PassCtx ctx_single(const IterScalars &s, const double *inv_norm) {
+    PassCtx c;
+    c.sigma = s.sigma;
+    c.lam_sigma = s.lam_sigma;
+    c.hx0 = s.hx0; c.hx1 = s.hx1; c.hy0 = s.hy0; c.hy1 = s.hy1;
+    c.inv_norm = inv_norm ? *inv_norm : 1.0;
+    c.m1_end = s.m1;
+    c.active = 1;
+    return c;
+}
+
+__device__ __forceinline__ PassCtx ctx_batch(const BatchArgs &b, int inst) {
+    PassCtx c;
+    c.active = b.active[inst];
+    const double sg = b.sigma[inst];
+    c.sigma = sg;
+    c.lam_sigma = b.lam[inst] * sg;
+    const double t = (double)((*b.kbase + b.iter_off) - b.kstart[inst]);
+    if (b.halpern) {
+        c.hx0 = 1.0 / (t + 1.0);
+        c.hx1 = t / (t + 1.0);
+        c.hy0 = 1.0 / (t + 2.0);
+        c.hy1 = (t + 1.0) / (t + 2.0);
+    } else {
+        c.hx0 = 0.0; c.hx1 = 1.0; c.hy0 = 0.0; c.hy1 = 1.0;
+    }
+    c.m1_end = b.m1_end[inst];
+    c.inv_norm = b.inv_norm ? b.inv_norm[inst] : 1.0;
+    return c;
+}
+
 // ------------------------------------------------------------------------- the SpMV kernel
 //
 // Op interface (one per pass kind):
-//   Raw raw(p)               nonzero p: column index and value, loaded with a streaming hint
-//   Sum prod(const Raw&)     gather of the input vector(s) and product
-//   Pre load(row)            epilogue operands of one row (prefetched when PREFETCH)
-//   void apply(row, sum, pre, inst, q)   the fused epilogue; q accumulates check terms
+//   PassCtx begin(inst)       scalars of the work item's instance
+//   Raw raw(p)                nonzero p: column index and value, loaded with a streaming hint
+//   Sum prod(const Raw&)      gather of the input vector(s) and product
+//   Pre load(row)             epilogue operands of one row (prefetched when PREFETCH)
+//   void apply(row, sum, pre, ctx, q)   the fused epilogue; q accumulates check terms
 // Loads are issued in batches of kEPT per thread (all indices/values first, then all
 // gathers) so each workgroup pays two memory latencies per batch instead of one per element.
 
@@ -136,73 +182,82 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
     for (int j = 0; j < NQ; ++j) q[j] = 0.0;
 
     if (kind == IT_TILE) {
-        S *prod = reinterpret_cast<S *>(smem);
-        S *rsum = prod + tile_cap;
-        int *rpl = reinterpret_cast<int *>(rsum + rows_cap);
         const int r0 = it.x, P0 = it.y, inst = it.z;
-        const int nrows = it.w >> 14, cnt = (it.w >> 2) & 4095;
-        const int r1 = r0 + nrows;
-        Pre pre[kRPT];
-        if constexpr (Op::PREFETCH) {
-            // rows past the tile re-load the tile's last row (valid, unused)
+        const PassCtx ctx = op.begin(inst);
+        if (ctx.active) {  // uniform over the workgroup
+            S *prod = reinterpret_cast<S *>(smem);
+            S *rsum = prod + tile_cap;
+            int *rpl = reinterpret_cast<int *>(rsum + rows_cap);
+            const int nrows = it.w >> 14, cnt = (it.w >> 2) & 4095;
+            const int r1 = r0 + nrows;
+            Pre pre[kRPT];
+            if constexpr (Op::PREFETCH) {
+                // rows past the tile re-load the tile's last row (valid, unused)
 #pragma unroll
-            for (int u = 0; u < kRPT; ++u) pre[u] = op.load(min(r0 + tid + u * kWG, r1 - 1));
-        }
-        // the tile's row pointers, staged in LDS for phase 2
-        int rpv[kRPT];
-#pragma unroll
-        for (int u = 0; u < kRPT; ++u) rpv[u] = rp[min(r0 + tid + u * kWG, r1 - 1)];
-        if (cnt > 0) {  // uniform: a tile of empty rows has no nonzeros to stream
-            typename Op::Raw raw[kEPT];
-#pragma unroll
-            for (int u = 0; u < kEPT; ++u) raw[u] = op.raw(P0 + min(tid + u * kWG, cnt - 1));
-            S v[kEPT];
-#pragma unroll
-            for (int u = 0; u < kEPT; ++u) v[u] = op.prod(raw[u]);
-#pragma unroll
-            for (int u = 0; u < kEPT; ++u) {
-                const int k = tid + u * kWG;
-                if (k < cnt) prod[k] = v[u];
+                for (int u = 0; u < kRPT; ++u) pre[u] = op.load(min(r0 + tid + u * kWG, r1 - 1));
             }
-        }
+            // the tile's row pointers, staged in LDS for phase 2
+            int rpv[kRPT];
 #pragma unroll
-        for (int u = 0; u < kRPT; ++u) {
-            const int rr = tid + u * kWG;
-            if (rr < nrows) rpl[rr] = rpv[u] - P0;
-        }
-        if (tid == 0) rpl[nrows] = cnt;
-        __syncthreads();
-        int G = 1;
-        while (G < 64 && 2 * G * nrows <= kWG) G <<= 1;
-        const int lg = tid & (G - 1);
-        const int ng = kWG / G;
-        for (int rr = tid / G; rr < nrows; rr += ng) {
-            const int b = rpl[rr], e = rpl[rr + 1];
-            S s = szero<S>();
-            for (int k = b + lg; k < e; k += G) s = s + prod[k];
-            for (int off = G >> 1; off > 0; off >>= 1) s = s + xshfl(s, off);
-            if (lg == 0) rsum[rr] = s;
-        }
-        __syncthreads();
+            for (int u = 0; u < kRPT; ++u) rpv[u] = rp[min(r0 + tid + u * kWG, r1 - 1)];
+            if (cnt > 0) {  // uniform: a tile of empty rows has no nonzeros to stream
+                typename Op::Raw raw[kEPT];
 #pragma unroll
-        for (int u = 0; u < kRPT; ++u) {
-            const int rr = tid + u * kWG;
-            if (rr < nrows) {
-                if constexpr (Op::PREFETCH) op.apply(r0 + rr, rsum[rr], pre[u], inst, q);
-                else op.apply(r0 + rr, rsum[rr], op.load(r0 + rr), inst, q);
+                for (int u = 0; u < kEPT; ++u) raw[u] = op.raw(P0 + min(tid + u * kWG, cnt - 1));
+                S v[kEPT];
+#pragma unroll
+                for (int u = 0; u < kEPT; ++u) v[u] = op.prod(raw[u]);
+#pragma unroll
+                for (int u = 0; u < kEPT; ++u) {
+                    const int k = tid + u * kWG;
+                    if (k < cnt) prod[k] = v[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRPT; ++u) {
+                const int rr = tid + u * kWG;
+                if (rr < nrows) rpl[rr] = rpv[u] - P0;
+            }
+            if (tid == 0) rpl[nrows] = cnt;
+            __syncthreads();
+            int G = 1;
+            while (G < 64 && 2 * G * nrows <= kWG) G <<= 1;
+            const int lg = tid & (G - 1);
+            const int ng = kWG / G;
+            for (int rr = tid / G; rr < nrows; rr += ng) {
+                const int b = rpl[rr], e = rpl[rr + 1];
+                S s = szero<S>();
+                for (int k = b + lg; k < e; k += G) s = s + prod[k];
+                for (int off = G >> 1; off > 0; off >>= 1) s = s + xshfl(s, off);
+                if (lg == 0) rsum[rr] = s;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kRPT; ++u) {
+                const int rr = tid + u * kWG;
+                if (rr < nrows) {
+                    if constexpr (Op::PREFETCH) op.apply(r0 + rr, rsum[rr], pre[u], ctx, q);
+                    else op.apply(r0 + rr, rsum[rr], op.load(r0 + rr), ctx, q);
+                }
             }
         }
     } else if (kind == IT_ROW) {
-        const int r = it.x, inst = it.w >> 2;
-        Pre pre{};
-        if (Op::PREFETCH && tid == 0) pre = op.load(r);
-        S s = row_sum(op, it.y, it.z, tid);
-        s = block_sum(s, red);
-        if (tid == 0) op.apply(r, s, Op::PREFETCH ? pre : op.load(r), inst, q);
+        const int r = it.x;
+        const PassCtx ctx = op.begin(it.w >> 2);
+        if (ctx.active) {
+            Pre pre{};
+            if (Op::PREFETCH && tid == 0) pre = op.load(r);
+            S s = row_sum(op, it.y, it.z, tid);
+            s = block_sum(s, red);
+            if (tid == 0) op.apply(r, s, Op::PREFETCH ? pre : op.load(r), ctx, q);
+        }
     } else if (kind == IT_CHUNK) {
-        S s = row_sum(op, it.x, it.y, tid);
-        s = block_sum(s, red);
-        if (tid == 0) split_part[it.z] = s;
+        const PassCtx ctx = op.begin(it.z);
+        if (ctx.active) {
+            S s = row_sum(op, it.x, it.y, tid);
+            s = block_sum(s, red);
+            if (tid == 0) split_part[it.w >> 2] = s;
+        }
     }  // IT_EMPTY: padding item, only the (zero) check partials below
     if constexpr (Op::NQ > 0) {
 #pragma unroll
@@ -221,15 +276,18 @@ __global__ __launch_bounds__(64) void k_split(const int4 *__restrict__ splits,
     using S = typename Op::Sum;
     constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
     const int4 sp = splits[blockIdx.x];
-    S s = szero<S>();
-    for (int k = threadIdx.x; k < sp.z; k += 64) s = s + part[sp.y + k];
-    s = wave_sum(s);
-    if (threadIdx.x == 0) {
-        double q[NQ];
+    const PassCtx ctx = op.begin(sp.w);
+    double q[NQ];
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) q[j] = 0.0;
-        op.apply(sp.x, s, op.load(sp.x), sp.w, q);
-        if constexpr (Op::NQ > 0) {
+    for (int j = 0; j < NQ; ++j) q[j] = 0.0;
+    if (ctx.active) {
+        S s = szero<S>();
+        for (int k = threadIdx.x; k < sp.z; k += 64) s = s + part[sp.y + k];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) op.apply(sp.x, s, op.load(sp.x), ctx, q);
+    }
+    if constexpr (Op::NQ > 0) {
+        if (threadIdx.x == 0) {
 #pragma unroll
             for (int j = 0; j < Op::NQ; ++j)
                 parts[(size_t)(slot_base + blockIdx.x) * Op::NQ + j] = q[j];
@@ -263,6 +321,23 @@ __global__ __launch_bounds__(kRedWG) void k_reduce(const double *__restrict__ pa
     }
 }
 
+// Segmented fixed-order reduction, one workgroup per instance b:
+// out[b * out_stride + j] = sum over the slots of b (in slot order) of parts[slot*nq + j].
+__global__ __launch_bounds__(kWG) void k_seg_reduce(const double *__restrict__ parts, int nq,
+                                                    const int *__restrict__ ptr,
+                                                    const int *__restrict__ slots,
+                                                    double *__restrict__ out, int out_stride) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const int s0 = ptr[b], s1 = ptr[b + 1];
+    for (int j = 0; j < nq; ++j) {
+        double s = 0.0;
+        for (int k = s0 + threadIdx.x; k < s1; k += kWG) s += parts[(size_t)slots[k] * nq + j];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) out[(size_t)b * out_stride + j] = s;
+    }
+}
+
 // ------------------------------------------------------------------------- epilogues
 
 // x-step over A^T (eqs. update-z/x): rows of A^T are the columns j of A.
@@ -270,7 +345,7 @@ __global__ __launch_bounds__(kRedWG) void k_reduce(const double *__restrict__ pa
 //   v      = x + sigma * s_j (g - c)             (s_j = dc_j^2 when the scaling is folded)
 //   x_bar  = Pi_C(v);   x_hat <- 2 x_bar - x     (gathered by the y-step)
 //   keep:  x_bar, z_int = (x_bar - v)/sigma (eq. update-z), dx = x - x_hat
-template <class M, class V, bool FOLD, bool KEEP> struct ColOp {
+template <class M, class V, bool FOLD, bool KEEP, bool B> struct ColOp {
     using Sum = typename AccT<M, V>::type;
     using Raw = RawT<M>;
     static constexpr int NQ = 0;
@@ -290,14 +365,20 @@ template <class M, class V, bool FOLD, bool KEEP> struct ColOp {
     V *__restrict__ xbar;
     V *__restrict__ zint;
     V *__restrict__ dx;
-    V sigma, hx0, hx1;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, nullptr);
+    }
     __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
     __device__ __forceinline__ Sum prod(const Raw &r) const { return (Sum)r.a * (Sum)yg[r.j]; }
     __device__ __forceinline__ Pre load(int j) const {
         return Pre{xhat[j], x0[j], cd[j], ld[j], ud[j], FOLD ? sc[j] : (V)1};
     }
-    __device__ __forceinline__ void apply(int j, Sum g, const Pre &p, int, double *) const {
-        const V x = hx0 * p.x0 + hx1 * p.xh;
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &p, const PassCtx &c,
+                                          double *) const {
+        const V sigma = (V)c.sigma;
+        const V x = (V)c.hx0 * p.x0 + (V)c.hx1 * p.xh;
         V gs = (V)g - p.cd;
         if (FOLD) gs = p.sc * gs;
         const V v = x + sigma * gs;
@@ -316,7 +397,7 @@ template <class M, class V, bool FOLD, bool KEEP> struct ColOp {
 //   y_bar = y + r_i (b - A x_hat)/(lambda sigma)  (r_i = dr_i^2 when folded);
 //   y_bar = max(y_bar, 0) on inequality rows;   y <- hy0 y0 + hy1 (2 y_bar - y)
 //   keep:  y_bar, dy = y - y_hat
-template <class M, class V, bool FOLD, bool KEEP> struct RowOp {
+template <class M, class V, bool FOLD, bool KEEP, bool B> struct RowOp {
     using Sum = typename AccT<M, V>::type;
     using Raw = RawT<M>;
     static constexpr int NQ = 0;
@@ -333,20 +414,24 @@ template <class M, class V, bool FOLD, bool KEEP> struct RowOp {
     const V *__restrict__ sr;
     V *__restrict__ ybar;
     V *__restrict__ dy;
-    V lam_sigma, hy0, hy1;
-    long long m1;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, nullptr);
+    }
     __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
     __device__ __forceinline__ Sum prod(const Raw &r) const { return (Sum)r.a * (Sum)xg[r.j]; }
     __device__ __forceinline__ Pre load(int i) const {
         return Pre{y[i], y0[i], bd[i], FOLD ? sr[i] : (V)1};
     }
-    __device__ __forceinline__ void apply(int i, Sum s, const Pre &p, int, double *) const {
-        V r = p.bd - (V)s;
+    __device__ __forceinline__ void apply(int i, Sum s_, const Pre &p, const PassCtx &c,
+                                          double *) const {
+        V r = p.bd - (V)s_;
         if (FOLD) r = p.sr * r;
-        V yb = p.y + r / lam_sigma;
-        if (i >= m1) yb = vmax(yb, (V)0);
+        V yb = p.y + r / (V)c.lam_sigma;
+        if (i >= c.m1_end) yb = vmax(yb, (V)0);
         const V yr = (V)2 * yb - p.y;
-        y[i] = hy0 * p.y0 + hy1 * yr;
+        y[i] = (V)c.hy0 * p.y0 + (V)c.hy1 * yr;
         if (KEEP) {
             ybar[i] = yb;
             dy[i] = p.y - yr;
@@ -358,7 +443,7 @@ template <class M, class V, bool FOLD, bool KEEP> struct RowOp {
 //   q0 = ||Pi_D(b - A x)||^2 (original data)   q1 = same on the scaled data (sigma update)
 //   q2 = <b, y_bar> / (beta_b beta_c)          q3 = ||dy||^2 (scaled)
 //   q4 = <dy, A~ dx>                           q5 = ||y_bar - y0||^2 (scaled)
-template <class M, class V> struct CheckRowOp {
+template <class M, class V, bool B> struct CheckRowOp {
     using Sum = D2;
     using Raw = RawT<M>;
     using Pre = NoPre;
@@ -375,17 +460,22 @@ template <class M, class V> struct CheckRowOp {
     const double *__restrict__ ro;
     const double *__restrict__ rs;
     const double *__restrict__ ys;
-    long long m1;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, nullptr);
+    }
     __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
     __device__ __forceinline__ Sum prod(const Raw &r) const {
         const double a = (double)r.a;
         return D2{a * (double)xbar[r.j], a * (double)dxv[r.j]};
     }
     __device__ __forceinline__ Pre load(int) const { return Pre{}; }
-    __device__ __forceinline__ void apply(int i, Sum s, const Pre &, int, double *q) const {
-        const double e = bd[i] - s.a;
+    __device__ __forceinline__ void apply(int i, Sum s_, const Pre &, const PassCtx &c,
+                                          double *q) const {
+        const double e = bd[i] - s_.a;
         double eo = ro[i] * e, es = rs[i] * e;
-        if (i >= m1) {
+        if (i >= c.m1_end) {
             eo = eo > 0.0 ? eo : 0.0;
             es = es > 0.0 ? es : 0.0;
         }
@@ -396,7 +486,7 @@ template <class M, class V> struct CheckRowOp {
         const double dyi = (double)dyv[i];
         const double d = ys[i] * dyi;
         q[3] += d * d;
-        q[4] += dyi * s.b;
+        q[4] += dyi * s_.b;
         const double e2 = ys[i] * (yb - (double)y0[i]);
         q[5] += e2 * e2;
     }
@@ -406,7 +496,7 @@ template <class M, class V> struct CheckRowOp {
 //   q0 = ||c - A^T y - z||^2 (original)   q1 = same on the scaled data
 //   q2 = <c, x_bar> / (beta_b beta_c)     q3 = delta*_C(-z) (original, 0*inf := 0)
 //   q4 = ||dx||^2 (scaled)                q5 = ||x_bar - x0||^2 (scaled)
-template <class M, class V, bool FOLD> struct CheckColOp {
+template <class M, class V, bool FOLD, bool B> struct CheckColOp {
     using Sum = double;
     using Raw = RawT<M>;
     using Pre = NoPre;
@@ -426,12 +516,18 @@ template <class M, class V, bool FOLD> struct CheckColOp {
     const double *__restrict__ xs;
     const double *__restrict__ lo;
     const double *__restrict__ uo;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, nullptr);
+    }
     __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
     __device__ __forceinline__ Sum prod(const Raw &r) const {
         return (double)r.a * (double)ybar[r.j];
     }
     __device__ __forceinline__ Pre load(int) const { return Pre{}; }
-    __device__ __forceinline__ void apply(int j, Sum g, const Pre &, int, double *q) const {
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &, const PassCtx &,
+                                          double *q) const {
         const double xb = (double)xbar[j];
         const double zi = (double)zint[j];
         double e = cd[j] - g;
@@ -455,7 +551,7 @@ template <class M, class V, bool FOLD> struct CheckColOp {
 
 // Power method on A~ A~^T (Section 4.1), FP64.  With the scaling folded, the vectors that
 // are gathered carry the diagonal factors: vg = D_r v, w = D_c A~^T v.
-template <class M, bool FOLD> struct PowColOp {
+template <class M, bool FOLD, bool B> struct PowColOp {
     using Sum = double;
     using Raw = RawT<M>;
     using Pre = NoPre;
@@ -467,18 +563,24 @@ template <class M, bool FOLD> struct PowColOp {
     const double *__restrict__ inv_norm;
     double *__restrict__ w;
     const double *__restrict__ sc;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, inv_norm);
+    }
     __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
     __device__ __forceinline__ Sum prod(const Raw &r) const { return (double)r.a * vg[r.j]; }
     __device__ __forceinline__ Pre load(int) const { return Pre{}; }
-    __device__ __forceinline__ void apply(int j, Sum g, const Pre &, int, double *q) const {
-        const double gn = g * (*inv_norm);
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &, const PassCtx &c,
+                                          double *q) const {
+        const double gn = g * c.inv_norm;
         const double t = FOLD ? sc[j] * gn : gn;
         w[j] = t;
         q[0] += t * gn;  // ||A~^T v||^2
     }
 };
 
-template <class M, bool FOLD> struct PowRowOp {
+template <class M, bool FOLD, bool B> struct PowRowOp {
     using Sum = double;
     using Raw = RawT<M>;
     using Pre = NoPre;
@@ -489,13 +591,19 @@ template <class M, bool FOLD> struct PowRowOp {
     const double *__restrict__ w;
     double *__restrict__ vg;
     const double *__restrict__ sr;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, nullptr);
+    }
     __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
     __device__ __forceinline__ Sum prod(const Raw &r) const { return (double)r.a * w[r.j]; }
     __device__ __forceinline__ Pre load(int) const { return Pre{}; }
-    __device__ __forceinline__ void apply(int i, Sum s, const Pre &, int, double *q) const {
-        const double t = FOLD ? sr[i] * s : s;
+    __device__ __forceinline__ void apply(int i, Sum s_, const Pre &, const PassCtx &,
+                                          double *q) const {
+        const double t = FOLD ? sr[i] * s_ : s_;
         vg[i] = t;
-        q[0] += t * s;  // ||A~ A~^T v||^2
+        q[0] += t * s_;  // ||A~ A~^T v||^2
     }
 };
 
@@ -515,6 +623,151 @@ __global__ __launch_bounds__(kRedWG) void k_power_reduce(const double *__restric
         *inv_norm = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
     }
 }
+
+// Batched power method: tmp[b] = ||A~_b^T v_b||^2, tmp[n + b] = ||A~_b A~_b^T v_b||^2.
+__global__ void k_power_finish(const double *__restrict__ tmp, int n_inst,
+                               double *__restrict__ hist_row, double *__restrict__ inv_norm) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_inst) return;
+    hist_row[b] = tmp[b];
+    const double t = tmp[n_inst + b];
+    inv_norm[b] = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+}
+
+// ------------------------------------------------------------------------- batched control
+
+// One workgroup of 1024 threads takes the decisions of every instance after a chunk: the
+// restart criteria of Section 3.1 on the merit R~ = ||w - w_hat||_M, SigmaUpdate (Algorithm 3
+// with eq. sigma_T1!=0), and the termination test of Section 4.1 on the original data.  It is
+// the device counterpart of the host loop of the single-LP solve, instance by instance.
+__global__ __launch_bounds__(kRedWG) void k_decide(DecideArgs d) {
+    __shared__ double red_a[kRedWG / 64], red_m[kRedWG / 64], red_s[kRedWG / 64];
+    double n_active = 0.0, max_kkt = 0.0, n_switch = 0.0;
+    const long long k0 = *d.kbase;          // iterations done before this chunk
+    const long long k = k0 + d.chunk;       // iterations done after it
+    for (int b = threadIdx.x; b < d.n_inst; b += kRedWG) {
+        d.restart_flag[b] = 0;
+        if (!d.active[b]) continue;
+        const double *qf = d.res_first + (size_t)b * 2 * kNQ;   // row sums, then column sums
+        const double *q = d.res_chk + (size_t)b * 2 * kNQ;
+        const double *cst = d.cst + (size_t)b * 8;
+        const double sigma = d.sigma[b], lam = d.lam[b];
+        const double m_first = sqrt(fmax(sigma * lam * qf[3] + 2.0 * qf[4] + qf[kNQ + 4] / sigma, 0.0));
+        const double merit = sqrt(fmax(sigma * lam * q[3] + 2.0 * q[4] + q[kNQ + 4] / sigma, 0.0));
+        if (d.kstart[b] == k0) {  // this chunk began a new outer loop for b: R~_{r,0}
+            d.merit0[b] = m_first;
+            d.merit_prev[b] = m_first;
+        }
+        const double bbc = cst[0] * cst[1];
+        const double rel_p = sqrt(q[0]) / (1.0 + cst[2]);
+        const double rel_d = sqrt(q[kNQ + 0]) / (1.0 + cst[3]);
+        const double pobj = bbc * q[kNQ + 2];
+        const double dobj = bbc * q[2] - q[kNQ + 3];
+        const double rel_gap = fabs(dobj - pobj) / (1.0 + fabs(dobj) + fabs(pobj));
+        double kkt = rel_p > rel_d ? rel_p : rel_d;
+        if (rel_gap > kkt) kkt = rel_gap;
+        double *last = d.last + (size_t)b * 6;
+        last[0] = rel_p; last[1] = rel_d; last[2] = rel_gap; last[3] = pobj; last[4] = dobj;
+        last[5] = merit;
+        const long long t = k - d.kstart[b];
+        const long long nc = d.nchecks[b];
+        double *tr = (nc < kTraceRows) ? d.trace + ((size_t)b * kTraceRows + nc) * kTraceCols : nullptr;
+        if (tr) {
+            tr[0] = (double)k; tr[1] = (double)t; tr[2] = (double)d.restarts[b]; tr[3] = sigma;
+            tr[4] = merit; tr[5] = rel_p; tr[6] = rel_d; tr[7] = rel_gap; tr[8] = 0.0;
+            tr[9] = sigma;
+        }
+        d.nchecks[b] = nc + 1;
+        int st = 0;
+        if (!(kkt == kkt)) st = HPRLP_NUMERICAL;
+        else if (kkt <= d.tol) st = HPRLP_OPTIMAL;
+        else if (k >= d.max_iter) st = HPRLP_ITER_LIMIT;
+        if (st) {
+            d.status[b] = st;
+            d.active[b] = 0;
+            d.iters_done[b] = k;
+            continue;
+        }
+        bool restart = false;
+        if (d.use_restart) {
+            const double m0 = d.merit0[b];
+            if (merit <= d.alpha1 * m0) restart = true;
+            if (merit <= d.alpha2 * m0 && merit > d.merit_prev[b]) restart = true;
+            if ((double)t >= d.alpha3 * (double)k) restart = true;
+        }
+        if (restart) {
+            double sig_new = sigma;
+            if (d.sigma_update) {
+                const double Dx = sqrt(q[kNQ + 5]);
+                const double Dy = sqrt(lam) * sqrt(q[5]);
+                const double err_p = sqrt(q[1]) / (1.0 + cst[4]);
+                const double err_d = sqrt(q[kNQ + 1]) / (1.0 + cst[5]);
+                const bool ok = Dx > 1e-16 && Dx < 1e12 && Dy > 1e-16 && Dy < 1e12 &&
+                                err_p > 0.0 && err_d / err_p > 1e-8 && err_d / err_p < 1e8;
+                sig_new = ok ? Dx / Dy : 1.0;
+            }
+            d.sigma[b] = sig_new;
+            d.kstart[b] = k;
+            d.restarts[b] += 1;
+            d.restart_flag[b] = 1;
+            if (tr) { tr[8] = 1.0; tr[9] = sig_new; }
+        } else {
+            d.merit_prev[b] = merit;
+        }
+        n_active += 1.0;
+        if (kkt > max_kkt) max_kkt = kkt;
+        if (kkt > d.tol_switch) n_switch += 1.0;
+    }
+    // summary for the host: instances still iterating, their largest rel. KKT, how many of
+    // them are still above the FP32 -> FP64 switch tolerance, iterations done
+    const double v = wave_sum(n_active);
+    const double w = wave_sum(n_switch);
+    double mk = max_kkt;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(mk, off, 64);
+        mk = o > mk ? o : mk;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red_a[threadIdx.x >> 6] = v;
+        red_m[threadIdx.x >> 6] = mk;
+        red_s[threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, m = 0.0, sw = 0.0;
+        for (int i = 0; i < kRedWG / 64; ++i) {
+            a += red_a[i];
+            sw += red_s[i];
+            m = red_m[i] > m ? red_m[i] : m;
+        }
+        d.summary[0] = a;
+        d.summary[1] = m;
+        d.summary[2] = sw;
+        d.summary[3] = (double)k;
+    }
+}
+
+// w^{r+1,0} = w_bar (anchors and current iterate) for the instances that restarted.
+template <class V>
+__global__ __launch_bounds__(kWG) void k_restart_batched(VecSet<V> v, const int *row_off,
+                                                         const int *col_off,
+                                                         const int *restart_flag) {
+    const int b = blockIdx.x;
+    if (!restart_flag[b]) return;
+    for (int j = col_off[b] + threadIdx.x; j < col_off[b + 1]; j += kWG) {
+        const V xb = v.xbar[j];
+        v.x0[j] = xb;
+        v.xhat[j] = xb;
+    }
+    for (int i = row_off[b] + threadIdx.x; i < row_off[b + 1]; i += kWG) {
+        const V yb = v.ybar[i];
+        v.y0[i] = yb;
+        v.y[i] = yb;
+    }
+}
+
+__global__ void k_advance(long long *kbase, int chunk) { *kbase += chunk; }
 
 // ------------------------------------------------------------------------- launch helpers
 
@@ -537,81 +790,111 @@ hipError_t run_pass(const DevMat &M, Op op, double *parts, hipStream_t st,
     return hipGetLastError();
 }
 
-template <class M, class V, bool FOLD, bool KEEP>
+template <class Op> void set_scalars(Op &op, const IterScalars &s, const BatchArgs *ba) {
+    op.s = s;
+    if (ba) op.ba = *ba;
+}
+
+template <class M, class V, bool FOLD, bool KEEP, bool B>
 hipError_t col_pass(const DevMat &T, const VecSet<V> &v, const IterScalars &s, hipStream_t st,
-                    hipEvent_t ev) {
-    ColOp<M, V, FOLD, KEEP> op;
+                    hipEvent_t ev, const BatchArgs *ba) {
+    ColOp<M, V, FOLD, KEEP, B> op;
     op.ci = T.ci;
     op.va = reinterpret_cast<const M *>(T.va);
     op.yg = v.y;
     op.xhat = v.xhat; op.x0 = v.x0; op.cd = v.cd; op.ld = v.ld; op.ud = v.ud; op.sc = v.sc;
     op.xbar = v.xbar; op.zint = v.zint; op.dx = v.dx;
-    op.sigma = (V)s.sigma; op.hx0 = (V)s.hx0; op.hx1 = (V)s.hx1;
+    set_scalars(op, s, ba);
     return run_pass(T, op, nullptr, st, ev);
 }
 
-template <class M, class V, bool FOLD, bool KEEP>
+template <class M, class V, bool FOLD, bool KEEP, bool B>
 hipError_t row_pass(const DevMat &A, const VecSet<V> &v, const IterScalars &s, hipStream_t st,
-                    hipEvent_t ev) {
-    RowOp<M, V, FOLD, KEEP> op;
+                    hipEvent_t ev, const BatchArgs *ba) {
+    RowOp<M, V, FOLD, KEEP, B> op;
     op.ci = A.ci;
     op.va = reinterpret_cast<const M *>(A.va);
     op.xg = v.xhat;
     op.y = v.y; op.y0 = v.y0; op.bd = v.bd; op.sr = v.sr; op.ybar = v.ybar; op.dy = v.dy;
-    op.lam_sigma = (V)s.lam_sigma; op.hy0 = (V)s.hy0; op.hy1 = (V)s.hy1;
-    op.m1 = s.m1;
+    set_scalars(op, s, ba);
     return run_pass(A, op, nullptr, st, ev);
 }
 
-template <class M, class V>
-hipError_t check_row(const DevMat &A, const VecSet<V> &v, const CheckData &cd, const double *bd,
-                     long long m1, double *parts, double *out, hipStream_t st) {
-    CheckRowOp<M, V> op;
-    op.ci = A.ci;
-    op.va = reinterpret_cast<const M *>(A.va);
-    op.xbar = v.xbar; op.dxv = v.dx; op.ybar = v.ybar; op.dyv = v.dy; op.y0 = v.y0;
-    op.bd = bd; op.ro = cd.ro; op.rs = cd.rs; op.ys = cd.ys; op.m1 = m1;
-    hipError_t e = run_pass(A, op, parts, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedWG), 0, st, parts, A.n_items + A.n_split, kNQ,
-                       out);
+hipError_t reduce_parts(const DevMat &M, double *parts, int nq, double *out, hipStream_t st,
+                        const Segments *seg, int out_stride) {
+    if (seg) {
+        if (seg->n_inst > 0)
+            hipLaunchKernelGGL(k_seg_reduce, dim3(seg->n_inst), dim3(kWG), 0, st, parts, nq,
+                               seg->ptr, seg->slots, out, out_stride);
+    } else {
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedWG), 0, st, parts,
+                           M.n_items + M.n_split, nq, out);
+    }
     return hipGetLastError();
 }
 
-template <class M, class V, bool FOLD>
+template <class M, class V, bool B>
+hipError_t check_row(const DevMat &A, const VecSet<V> &v, const CheckData &cd, const double *bd,
+                     long long m1, double *parts, double *out, hipStream_t st,
+                     const BatchArgs *ba, const Segments *seg, int out_stride) {
+    CheckRowOp<M, V, B> op;
+    op.ci = A.ci;
+    op.va = reinterpret_cast<const M *>(A.va);
+    op.xbar = v.xbar; op.dxv = v.dx; op.ybar = v.ybar; op.dyv = v.dy; op.y0 = v.y0;
+    op.bd = bd; op.ro = cd.ro; op.rs = cd.rs; op.ys = cd.ys;
+    IterScalars s{};
+    s.m1 = m1;
+    set_scalars(op, s, ba);
+    hipError_t e = run_pass(A, op, parts, st);
+    if (e != hipSuccess) return e;
+    return reduce_parts(A, parts, kNQ, out, st, seg, out_stride);
+}
+
+template <class M, class V, bool FOLD, bool B>
 hipError_t check_col(const DevMat &T, const VecSet<V> &v, const CheckData &cd, const double *cdv,
-                     const double *sc, double *parts, double *out, hipStream_t st) {
-    CheckColOp<M, V, FOLD> op;
+                     const double *sc, double *parts, double *out, hipStream_t st,
+                     const BatchArgs *ba, const Segments *seg, int out_stride) {
+    CheckColOp<M, V, FOLD, B> op;
     op.ci = T.ci;
     op.va = reinterpret_cast<const M *>(T.va);
     op.ybar = v.ybar; op.xbar = v.xbar; op.zint = v.zint; op.dxv = v.dx; op.x0 = v.x0;
     op.cd = cdv; op.sc = sc; op.co = cd.co; op.cs = cd.cs; op.xs = cd.xs;
     op.lo = cd.lo; op.uo = cd.uo;
+    set_scalars(op, IterScalars{}, ba);
     hipError_t e = run_pass(T, op, parts, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedWG), 0, st, parts, T.n_items + T.n_split, kNQ,
-                       out);
-    return hipGetLastError();
+    return reduce_parts(T, parts, kNQ, out, st, seg, out_stride);
 }
 
-template <class M, bool FOLD>
+template <class M, bool FOLD, bool B>
 hipError_t power_iter(const DevMat &A, const DevMat &T, double *vg, double *w, const double *sc,
                       const double *sr, double *inv_norm, double *pc, double *pr, double *hist,
-                      hipStream_t st) {
-    PowColOp<M, FOLD> oc;
+                      hipStream_t st, const BatchArgs *ba, const Segments *segA,
+                      const Segments *segT, double *seg_tmp) {
+    PowColOp<M, FOLD, B> oc;
     oc.ci = T.ci;
     oc.va = reinterpret_cast<const M *>(T.va);
     oc.vg = vg; oc.inv_norm = inv_norm; oc.w = w; oc.sc = sc;
+    set_scalars(oc, IterScalars{}, ba);
     hipError_t e = run_pass(T, oc, pc, st);
     if (e != hipSuccess) return e;
-    PowRowOp<M, FOLD> orw;
+    PowRowOp<M, FOLD, B> orw;
     orw.ci = A.ci;
     orw.va = reinterpret_cast<const M *>(A.va);
     orw.w = w; orw.vg = vg; orw.sr = sr;
+    set_scalars(orw, IterScalars{}, ba);
     e = run_pass(A, orw, pr, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_power_reduce, dim3(1), dim3(kRedWG), 0, st, pc, T.n_items + T.n_split,
-                       pr, A.n_items + A.n_split, hist, inv_norm);
+    if (!B) {
+        hipLaunchKernelGGL(k_power_reduce, dim3(1), dim3(kRedWG), 0, st, pc,
+                           T.n_items + T.n_split, pr, A.n_items + A.n_split, hist, inv_norm);
+        return hipGetLastError();
+    }
+    const int n = segA->n_inst;
+    if ((e = reduce_parts(T, pc, 1, seg_tmp, st, segT, 1)) != hipSuccess) return e;
+    if ((e = reduce_parts(A, pr, 1, seg_tmp + n, st, segA, 1)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_power_finish, dim3((n + 255) / 256), dim3(256), 0, st, seg_tmp, n,
+                       hist, const_cast<double *>(ba->inv_norm));
     return hipGetLastError();
 }
 
@@ -655,76 +938,105 @@ inline dim3 grid_for(long long n) {
 
 // ------------------------------------------------------------------------- dispatch
 
+#define HPRLP_PREC_DISPATCH(CALL)                                                               \
+    do {                                                                                       \
+        if (prec == 0) {                                                                       \
+            auto &v = *static_cast<const VecSet<double> *>(vs);                                \
+            return CALL(double, double, false);                                                \
+        }                                                                                      \
+        if (prec == 1) {                                                                       \
+            auto &v = *static_cast<const VecSet<float> *>(vs);                                 \
+            return CALL(float, float, true);                                                   \
+        }                                                                                      \
+        auto &v = *static_cast<const VecSet<double> *>(vs);                                    \
+        return CALL(float, double, true);                                                      \
+    } while (0)
+
 hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vs,
-                           const IterScalars &s, hipStream_t st, hipEvent_t ev) {
-    if (prec == 0) {
-        auto &v = *static_cast<const VecSet<double> *>(vs);
-        return keep ? col_pass<double, double, false, true>(T, v, s, st, ev)
-                    : col_pass<double, double, false, false>(T, v, s, st, ev);
-    }
-    if (prec == 1) {
-        auto &v = *static_cast<const VecSet<float> *>(vs);
-        return keep ? col_pass<float, float, true, true>(T, v, s, st, ev)
-                    : col_pass<float, float, true, false>(T, v, s, st, ev);
-    }
-    auto &v = *static_cast<const VecSet<double> *>(vs);
-    return keep ? col_pass<float, double, true, true>(T, v, s, st, ev)
-                : col_pass<float, double, true, false>(T, v, s, st, ev);
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev,
+                           const BatchArgs *ba) {
+#define COL_CALL(M, V, F)                                                                       \
+    (ba ? (keep ? col_pass<M, V, F, true, true>(T, v, s, st, ev, ba)                           \
+                : col_pass<M, V, F, false, true>(T, v, s, st, ev, ba))                         \
+        : (keep ? col_pass<M, V, F, true, false>(T, v, s, st, ev, ba)                          \
+                : col_pass<M, V, F, false, false>(T, v, s, st, ev, ba)))
+    HPRLP_PREC_DISPATCH(COL_CALL);
+#undef COL_CALL
 }
 
 hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vs,
-                           const IterScalars &s, hipStream_t st, hipEvent_t ev) {
-    if (prec == 0) {
-        auto &v = *static_cast<const VecSet<double> *>(vs);
-        return keep ? row_pass<double, double, false, true>(A, v, s, st, ev)
-                    : row_pass<double, double, false, false>(A, v, s, st, ev);
-    }
-    if (prec == 1) {
-        auto &v = *static_cast<const VecSet<float> *>(vs);
-        return keep ? row_pass<float, float, true, true>(A, v, s, st, ev)
-                    : row_pass<float, float, true, false>(A, v, s, st, ev);
-    }
-    auto &v = *static_cast<const VecSet<double> *>(vs);
-    return keep ? row_pass<float, double, true, true>(A, v, s, st, ev)
-                : row_pass<float, double, true, false>(A, v, s, st, ev);
+                           const IterScalars &s, hipStream_t st, hipEvent_t ev,
+                           const BatchArgs *ba) {
+#define ROW_CALL(M, V, F)                                                                       \
+    (ba ? (keep ? row_pass<M, V, F, true, true>(A, v, s, st, ev, ba)                           \
+                : row_pass<M, V, F, false, true>(A, v, s, st, ev, ba))                         \
+        : (keep ? row_pass<M, V, F, true, false>(A, v, s, st, ev, ba)                          \
+                : row_pass<M, V, F, false, false>(A, v, s, st, ev, ba)))
+    HPRLP_PREC_DISPATCH(ROW_CALL);
+#undef ROW_CALL
 }
 
 hipError_t launch_check_row(int prec, const DevMat &A, const void *vs, const CheckData &cd,
                             const double *bd64, long long m1, double *parts, double *out,
-                            hipStream_t st) {
-    if (prec == 0)
-        return check_row<double, double>(A, *static_cast<const VecSet<double> *>(vs), cd, bd64,
-                                         m1, parts, out, st);
-    if (prec == 1)
-        return check_row<float, float>(A, *static_cast<const VecSet<float> *>(vs), cd, bd64, m1,
-                                       parts, out, st);
-    return check_row<float, double>(A, *static_cast<const VecSet<double> *>(vs), cd, bd64, m1,
-                                    parts, out, st);
+                            hipStream_t st, const BatchArgs *ba, const Segments *seg,
+                            int out_stride) {
+#define CR_CALL(M, V, F)                                                                        \
+    (ba ? check_row<M, V, true>(A, v, cd, bd64, m1, parts, out, st, ba, seg, out_stride)       \
+        : check_row<M, V, false>(A, v, cd, bd64, m1, parts, out, st, ba, seg, out_stride))
+    HPRLP_PREC_DISPATCH(CR_CALL);
+#undef CR_CALL
 }
 
 hipError_t launch_check_col(int prec, const DevMat &T, const void *vs, const CheckData &cd,
                             const double *cd64, const double *sc64, double *parts, double *out,
-                            hipStream_t st) {
-    if (prec == 0)
-        return check_col<double, double, false>(T, *static_cast<const VecSet<double> *>(vs), cd,
-                                                 cd64, nullptr, parts, out, st);
-    if (prec == 1)
-        return check_col<float, float, true>(T, *static_cast<const VecSet<float> *>(vs), cd, cd64,
-                                             sc64, parts, out, st);
-    return check_col<float, double, true>(T, *static_cast<const VecSet<double> *>(vs), cd, cd64,
-                                          sc64, parts, out, st);
+                            hipStream_t st, const BatchArgs *ba, const Segments *seg,
+                            int out_stride) {
+#define CC_CALL(M, V, F)                                                                        \
+    (ba ? check_col<M, V, F, true>(T, v, cd, cd64, sc64, parts, out, st, ba, seg, out_stride)  \
+        : check_col<M, V, F, false>(T, v, cd, cd64, sc64, parts, out, st, ba, seg, out_stride))
+    HPRLP_PREC_DISPATCH(CC_CALL);
+#undef CC_CALL
 }
 
 hipError_t launch_power_iter(bool mat_f32, bool fold, const DevMat &A, const DevMat &T,
                              double *vg, double *w, const double *sc, const double *sr,
                              double *inv_norm, double *pc, double *pr, double *hist, int k,
-                             hipStream_t st) {
-    if (mat_f32) {
-        return fold ? power_iter<float, true>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st)
-                    : power_iter<float, false>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st);
-    }
-    return fold ? power_iter<double, true>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st)
-                : power_iter<double, false>(A, T, vg, w, sc, sr, inv_norm, pc, pr, hist + k, st);
+                             hipStream_t st, const BatchArgs *ba, const Segments *segA,
+                             const Segments *segT, double *seg_tmp) {
+    double *h = ba ? hist + (size_t)k * segA->n_inst : hist + k;
+#define PW(M, F)                                                                                \
+    (ba ? power_iter<M, F, true>(A, T, vg, w, sc, sr, inv_norm, pc, pr, h, st, ba, segA, segT,  \
+                                 seg_tmp)                                                      \
+        : power_iter<M, F, false>(A, T, vg, w, sc, sr, inv_norm, pc, pr, h, st, ba, segA,       \
+                                  segT, seg_tmp))
+    if (mat_f32) return fold ? PW(float, true) : PW(float, false);
+    return fold ? PW(double, true) : PW(double, false);
+#undef PW
+}
+
+hipError_t launch_decide(const DecideArgs &d, hipStream_t st) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kRedWG), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_restart_batched(bool f32, const void *vs, const int *row_off,
+                                  const int *col_off, const int *restart_flag, int n_inst,
+                                  hipStream_t st) {
+    if (n_inst <= 0) return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL(k_restart_batched<float>, dim3(n_inst), dim3(kWG), 0, st,
+                           *static_cast<const VecSet<float> *>(vs), row_off, col_off,
+                           restart_flag);
+    else
+        hipLaunchKernelGGL(k_restart_batched<double>, dim3(n_inst), dim3(kWG), 0, st,
+                           *static_cast<const VecSet<double> *>(vs), row_off, col_off,
+                           restart_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(long long *kbase, int chunk, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, st, kbase, chunk);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t st) {

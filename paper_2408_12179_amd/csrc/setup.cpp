@@ -203,7 +203,8 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
                 for (int c = 0; c < nch; ++c) {
                     const int64_t p0 = rowptr[r] + (int64_t)c * sp.chunk_nnz;
                     const int64_t p1 = std::min(rowptr[r + 1], p0 + sp.chunk_nnz);
-                    chunks.push_back(make_int4((int)p0, (int)p1, out.n_chunk_slots + c, IT_CHUNK));
+                    chunks.push_back(make_int4((int)p0, (int)p1, inst(r),
+                                               ((out.n_chunk_slots + c) << 2) | IT_CHUNK));
                 }
                 out.n_chunk_slots += nch;
             }

@@ -24,9 +24,13 @@ XBAR, YBAR, ZBAR, XCUR, YCUR, DROW, DCOL = range(7)
 TRACE_COLS = ["k", "t", "r", "sigma", "merit", "merit0", "merit_prev", "rel_p", "rel_d",
               "rel_gap", "pobj", "dobj", "dx", "dy", "err_p", "err_d", "restart",
               "sigma_new"]
-EXPORTS = ["hprlp_default_options", "hprlp_workspace_bytes", "hprlp_create", "hprlp_solve",
-           "hprlp_stats", "hprlp_get_iterate", "hprlp_get_trace", "hprlp_time_passes",
-           "hprlp_last_error", "hprlp_destroy"]
+BATCH_TRACE_COLS = ["k", "t", "r", "sigma", "merit", "rel_p", "rel_d", "rel_gap", "restart",
+                    "sigma_new"]
+EXPORTS = ["hprlp_default_options", "hprlp_workspace_bytes", "hprlp_workspace_bytes_batched",
+           "hprlp_create", "hprlp_create_batched", "hprlp_solve", "hprlp_stats",
+           "hprlp_stats_instance", "hprlp_get_iterate", "hprlp_get_trace",
+           "hprlp_get_trace_instance", "hprlp_time_passes", "hprlp_last_error",
+           "hprlp_destroy"]
 
 
 class Options(C.Structure):
@@ -87,6 +91,13 @@ def load() -> C.CDLL:
                                           C.POINTER(Options), C.POINTER(C.c_size_t)]
     lib.hprlp_create.argtypes = [C.POINTER(P), C.c_int64, C.c_int64, C.c_int64, P, P, P, P, P,
                                  P, P, C.POINTER(Options), P, C.c_size_t, P]
+    lib.hprlp_workspace_bytes_batched.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int64,
+                                                  C.POINTER(Options), C.POINTER(C.c_size_t)]
+    lib.hprlp_create_batched.argtypes = [C.POINTER(P), C.c_int32, P, P, P, P, P, P, P, P, P, P,
+                                         P, C.POINTER(Options), P, C.c_size_t, P]
+    lib.hprlp_stats_instance.argtypes = [P, C.c_int32, C.POINTER(Stats)]
+    lib.hprlp_get_trace_instance.argtypes = [P, C.c_int32, P, C.c_longlong,
+                                             C.POINTER(C.c_longlong)]
     lib.hprlp_solve.argtypes = [P, P, P, P, C.POINTER(C.c_int)]
     lib.hprlp_stats.argtypes = [P, C.POINTER(Stats)]
     lib.hprlp_get_iterate.argtypes = [P, C.c_int, P]
@@ -96,8 +107,9 @@ def load() -> C.CDLL:
     lib.hprlp_last_error.restype = C.c_char_p
     lib.hprlp_destroy.argtypes = [P]
     lib.hprlp_destroy.restype = None
-    for name in EXPORTS[1:-2]:
-        getattr(lib, name).restype = C.c_int
+    for name in EXPORTS:
+        if name not in ("hprlp_default_options", "hprlp_last_error", "hprlp_destroy"):
+            getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
 
@@ -128,6 +140,14 @@ def workspace_bytes(m1: int, m2: int, n: int, nnz: int, opts: Options) -> int:
     return int(out.value)
 
 
+def workspace_bytes_batched(n_inst: int, m: int, n: int, nnz: int, opts: Options) -> int:
+    out = C.c_size_t()
+    rc = load().hprlp_workspace_bytes_batched(n_inst, m, n, nnz, C.byref(opts), C.byref(out))
+    if rc != OK:
+        raise HPRLPError(rc, last_error())
+    return int(out.value)
+
+
 @dataclass
 class Solution:
     x: np.ndarray
@@ -139,14 +159,20 @@ class Solution:
 
 class Solver:
     """One LP on one GPU.  ``lp`` is any object with m1, m2, n, rowptr, colidx, val, b, c, l,
-    u attributes (e.g. ``lpgen.LP``); options are the fields of ``hprlp_options``."""
+    u attributes (e.g. ``lpgen.LP``); options are the fields of ``hprlp_options``.
 
-    def __init__(self, lp, device: int = 0, **options):
+    ``batched=True`` solves the independent LPs packed block-diagonally in ``lp`` (which then
+    also carries inst_row_off, inst_col_off, inst_m1) in one run; ``lambdas`` optionally
+    gives lambda per instance."""
+
+    def __init__(self, lp, device: int = 0, batched: bool = False, lambdas=None, **options):
         import torch  # device memory and stream only
         lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HPR-LP library runs on an MI355X only")
         self._lib = lib
+        self._h = None
+        self.batched = batched
         self.m1, self.m2, self.n = int(lp.m1), int(lp.m2), int(lp.n)
         self.m = self.m1 + self.m2
         self._arrays = [np.ascontiguousarray(lp.rowptr, dtype=np.int64),
@@ -154,15 +180,32 @@ class Solver:
             [np.ascontiguousarray(a, dtype=np.float64) for a in (lp.val, lp.b, lp.c, lp.l, lp.u)]
         self.opts = default_options(**options)
         nnz = int(self._arrays[0][-1])
-        nbytes = workspace_bytes(self.m1, self.m2, self.n, nnz, self.opts)
+        if batched:
+            self._inst = [np.ascontiguousarray(a, dtype=np.int64)
+                          for a in (lp.inst_row_off, lp.inst_col_off, lp.inst_m1)]
+            self.n_inst = len(self._inst[2])
+            self._lams = None if lambdas is None else \
+                np.ascontiguousarray(lambdas, dtype=np.float64)
+            if self._lams is not None and len(self._lams) != self.n_inst:
+                raise ValueError("lambdas needs one value per instance")
+            nbytes = workspace_bytes_batched(self.n_inst, self.m, self.n, nnz, self.opts)
+        else:
+            self.n_inst = 1
+            nbytes = workspace_bytes(self.m1, self.m2, self.n, nnz, self.opts)
         self.device = torch.device("cuda", device)
         self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        rc = lib.hprlp_create(C.byref(h), self.m1, self.m2, self.n,
-                              *[_ptr(a) for a in self._arrays], C.byref(self.opts),
-                              C.c_void_p(self._ws.data_ptr()), nbytes,
-                              C.c_void_p(self._stream.cuda_stream))
+        ws = C.c_void_p(self._ws.data_ptr())
+        stream = C.c_void_p(self._stream.cuda_stream)
+        if batched:
+            rc = lib.hprlp_create_batched(C.byref(h), self.n_inst, *[_ptr(a) for a in self._inst],
+                                          *[_ptr(a) for a in self._arrays], _ptr(self._lams),
+                                          C.byref(self.opts), ws, nbytes, stream)
+        else:
+            rc = lib.hprlp_create(C.byref(h), self.m1, self.m2, self.n,
+                                  *[_ptr(a) for a in self._arrays], C.byref(self.opts), ws,
+                                  nbytes, stream)
         if rc != OK:
             raise HPRLPError(rc, last_error())
         self._h = h
@@ -195,6 +238,19 @@ class Solver:
         s = Stats()
         self._check(self._lib.hprlp_stats(self._h, C.byref(s)))
         return s.as_dict()
+
+    def stats_instance(self, i: int) -> dict:
+        s = Stats()
+        self._check(self._lib.hprlp_stats_instance(self._h, i, C.byref(s)))
+        return s.as_dict()
+
+    def trace_instance(self, i: int) -> np.ndarray:
+        n = C.c_longlong()
+        self._check(self._lib.hprlp_get_trace_instance(self._h, i, None, 0, C.byref(n)))
+        out = np.zeros((n.value, len(BATCH_TRACE_COLS)))
+        self._check(self._lib.hprlp_get_trace_instance(self._h, i, _ptr(out), n.value,
+                                                       C.byref(n)))
+        return out
 
     def iterate(self, which: int) -> np.ndarray:
         size = self.m if which in (YBAR, YCUR, DROW) else self.n

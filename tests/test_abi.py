@@ -154,3 +154,72 @@ def test_null_out_pointer(lib):
     rc = lib.hprlp_create(None, 1, 0, 1, None, None, None, None, None, None, None, C.byref(o),
                           None, 0, None)
     assert rc == hprlp.EINVAL
+
+
+def _create_batched(lib, lp, row_off, col_off, m1s, lams=None, ws=257, **opt):
+    # ws is a misaligned fake pointer: a case that wrongly passed validation would stop at
+    # the workspace check instead of reaching the GPU
+    o = hprlp.default_options(**opt)
+    arrs = [np.ascontiguousarray(lp.rowptr, dtype=np.int64),
+            np.ascontiguousarray(lp.colidx, dtype=np.int32)] + \
+        [np.ascontiguousarray(a, dtype=np.float64) for a in (lp.val, lp.b, lp.c, lp.l, lp.u)]
+    inst = [np.ascontiguousarray(a, dtype=np.int64) for a in (row_off, col_off, m1s)]
+    lam = None if lams is None else np.ascontiguousarray(lams, dtype=np.float64)
+    h = C.c_void_p()
+    rc = lib.hprlp_create_batched(C.byref(h), len(m1s), *[C.c_void_p(a.ctypes.data) for a in inst],
+                                  *[C.c_void_p(a.ctypes.data) for a in arrs],
+                                  None if lam is None else C.c_void_p(lam.ctypes.data),
+                                  C.byref(o), C.c_void_p(ws), 1 << 30, None)
+    return rc, lib.hprlp_last_error(None).decode()
+
+
+def _two_instances():
+    a = lpgen.bernoulli_lp(10, 10, 40, 0.2, seed=3)
+    b = lpgen.bernoulli_lp(5, 15, 30, 0.2, seed=4)
+    return lpgen.pack_block_diagonal([a, b])
+
+
+@pytest.mark.parametrize("case,code", [
+    ("offsets_do_not_start_at_0", hprlp.EDIM),
+    ("offsets_not_increasing", hprlp.EDIM),
+    ("m1_too_large", hprlp.EDIM),
+    ("row_crosses_instances", hprlp.EDIM),
+    ("check_every_one", hprlp.EINVAL),
+    ("bad_lambda", hprlp.EINVAL),
+    ("no_instances", hprlp.EDIM),
+])
+def test_create_batched_rejects_bad_layout(lib, case, code):
+    lp = _two_instances()
+    ro, co, m1s = lp.inst_row_off.copy(), lp.inst_col_off.copy(), lp.inst_m1.copy()
+    opt, lams = {}, None
+    if case == "offsets_do_not_start_at_0":
+        ro[0] = 1
+    elif case == "offsets_not_increasing":
+        co[1] = 0
+    elif case == "m1_too_large":
+        m1s[0] = ro[1] - ro[0] + 1
+    elif case == "row_crosses_instances":
+        # move the first nonzero of instance 1 into instance 0's columns
+        lp.colidx[lp.rowptr[ro[1]]] = 0
+        lp.colidx[lp.rowptr[ro[1]]:lp.rowptr[ro[1] + 1]].sort()
+        if len(set(lp.colidx[lp.rowptr[ro[1]]:lp.rowptr[ro[1] + 1]])) < \
+                lp.rowptr[ro[1] + 1] - lp.rowptr[ro[1]]:
+            pytest.skip("row became a repeat")
+    elif case == "check_every_one":
+        opt = dict(check_every=1)
+    elif case == "bad_lambda":
+        lams = [1.0, -2.0]
+    else:
+        m1s = m1s[:0]
+    rc, msg = _create_batched(lib, lp, ro, co, m1s, lams, **opt)
+    assert rc == code, (rc, msg)
+    assert msg and "workspace" not in msg
+
+
+def test_workspace_bytes_batched(lib):
+    o = hprlp.default_options()
+    a = hprlp.workspace_bytes_batched(4, 400, 800, 4000, o)
+    assert a > hprlp.workspace_bytes(200, 200, 800, 4000, o)  # per-instance arrays on top
+    with pytest.raises(hprlp.HPRLPError) as e:
+        hprlp.workspace_bytes_batched(500, 400, 800, 4000, o)  # more instances than rows
+    assert e.value.code == hprlp.EDIM
