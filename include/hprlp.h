@@ -100,6 +100,10 @@ typedef struct {
     int profile;             /* N > 0: time the passes of every N-th iteration with HIP    */
                              /* events (stats col/row_pass_ms); 0: off                     */
     int verbose;             /* 1: one log line per check on stderr                        */
+    int autotune;            /* 1: at create, time candidate schedules of A and A^T on the  */
+                             /* uploaded problem and keep the fastest per matrix (problems  */
+                             /* with >= 1e5 nonzeros); the schedule fields above are then   */
+                             /* the starting point.  0 (default): use them as given         */
 } hprlp_options;
 
 typedef struct {
@@ -120,6 +124,8 @@ typedef struct {
     long long col_pass_launches, row_pass_launches;
     double split_ms;         /* profile=1: summed time of the split-row finishing kernels  */
     long long n_checks;
+    long long n_compactions; /* batched: times the schedules were rebuilt without the      */
+                             /* instances that had stopped                                  */
 } hprlp_stats_t;
 
 /* Iterates that hprlp_get_iterate can return (original space unless noted). */
@@ -223,6 +229,14 @@ int hprlp_get_trace(const hprlp_handle *h, double *out, long long cap, long long
  * *n_rows.  EINVAL on a single-LP handle. */
 int hprlp_get_trace_instance(const hprlp_handle *h, int32_t i, double *out, long long cap,
                              long long *n_rows);
+
+/* Schedule in use for A (matrix = 0, the row pass) or A^T (matrix = 1, the column pass):
+ * params[5] = {tile_nnz, tile_rows, short_max, split_len, chunk_nnz} (nullable),
+ * counts[4] = {work items incl. padding, tiles, whole-workgroup rows, split chunks}
+ * (nullable), *tuned_ms = the autotuner's measured time of one pass launch with it (0 when
+ * the autotuner did not run; nullable).  Host only. */
+int hprlp_get_schedule(const hprlp_handle *h, int matrix, int32_t *params, int64_t *counts,
+                       double *tuned_ms);
 
 /* Time the two iteration passes on the current state: `reps` launches of the column pass
  * (x-step over A~^T) and of the row pass (y-step over A~), each bracketed by HIP events on

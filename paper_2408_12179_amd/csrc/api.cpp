@@ -53,6 +53,17 @@ struct Carver {
     template <class T> T *arr(size_t n) { return static_cast<T *>(take(n * sizeof(T))); }
 };
 
+// Candidate values of the schedule autotuner, tried by coordinate descent per matrix: tile
+// shape, then the longest row kept in tiles, then the split of very long rows.
+constexpr int kTuneTileNnz[] = {1024, 2048};
+constexpr int kTuneTileRows[] = {128, 256, 512, 1024};
+constexpr int kTuneShortMax[] = {16, 32, 64, 128, 256, 512, 1024, 2048};
+constexpr int kTuneSplitLen[] = {2048, 4096, 8192, 16384, 65536};
+constexpr int kTuneChunk[] = {2048, 4096, 8192};
+constexpr int kTuneMinChunk = 2048, kTuneMinSplit = 2048;
+constexpr int64_t kTuneMinNnz = 100000;  // below this a pass is launch-bound: keep the defaults
+constexpr int kTuneReps = 10;
+
 // Device arrays of a batched solve (one entry per instance unless noted).
 struct BatchDev {
     double *sigma = nullptr, *lam = nullptr, *merit0 = nullptr, *merit_prev = nullptr;
@@ -101,6 +112,17 @@ struct hprlp_handle {
     std::vector<double> lam_given;          // per-instance lambda from the caller (or empty)
     hipGraphExec_t graphs[3] = {nullptr, nullptr, nullptr};
     std::vector<hprlp_stats_t> inst_stats;
+    // schedule parameters of A and A^T (the autotuner may pick different ones per matrix)
+    ScheduleParams spA{}, spT{};
+    double tuned_ms[2] = {0.0, 0.0};          // autotuner: best row / column pass time
+    // schedules over the instances still iterating (rebuilt as instances stop)
+    std::vector<int64_t> rpA, rpT;            // host row pointers of A and A^T
+    std::vector<int32_t> inst_row, inst_col;  // instance of every row and column
+    std::vector<int64_t> inst_nnz;            // nonzeros of every instance
+    int capA[3] = {0, 0, 0}, capT[3] = {0, 0, 0};  // carved items, splits, chunk slots
+    int64_t sched_nnz = 0;                    // nonzeros covered by the current schedules
+    bool compacted = false;
+    long long n_compactions = 0;
     // solve state (single LP)
     int prec = 0;
     long long t = 0, k = 0, r = 0;
@@ -236,13 +258,16 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n
     Plan p;
     p.m = m; p.n = n; p.nnz = nnz; p.mixed = o.precision != HPRLP_FP64;
     p.f32phase = o.precision == HPRLP_MIXED;
-    const int64_t ch = nnz / o.chunk_nnz + 1;
+    // with the autotuner on, room for every candidate schedule (smallest chunk and split)
+    const int chunk = o.autotune ? std::min(o.chunk_nnz, kTuneMinChunk) : o.chunk_nnz;
+    const int split = o.autotune ? std::min(o.split_len, kTuneMinSplit) : o.split_len;
+    const int64_t ch = nnz / chunk + 1;
     // padding items: at most kXCD-1 per class segment (chunks, tiles, and each equal-length
     // run of whole-workgroup rows, which has >= 16*kXCD rows): bounded by kXCD + rows/16
     p.itemsA = (int)std::min<int64_t>(2 * m + ch + 3 * kXCD + m / 16, INT32_MAX / 8);
     p.itemsT = (int)std::min<int64_t>(2 * n + ch + 3 * kXCD + n / 16, INT32_MAX / 8);
-    p.splitA = (int)std::min<int64_t>(m, nnz / o.split_len + 1);
-    p.splitT = (int)std::min<int64_t>(n, nnz / o.split_len + 1);
+    p.splitA = (int)std::min<int64_t>(m, nnz / split + 1);
+    p.splitT = (int)std::min<int64_t>(n, nnz / split + 1);
     p.slotsA = (int)ch + p.splitA;
     p.slotsT = (int)ch + p.splitT;
     p.power_cap = power_cap(o);
@@ -476,6 +501,9 @@ int validate_layout(const Layout &L, int64_t m, int64_t n, const int64_t *rowptr
     return HPRLP_OK;
 }
 
+int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
+                   const int32_t *inst_row, const int32_t *inst_col);
+
 // Shared body of hprlp_create and hprlp_create_batched.
 int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
                 const int32_t *colidx, const double *val, const double *b, const double *c,
@@ -615,17 +643,21 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     h->bsnorm = cst[0][4];
     h->csnorm = cst[0][5];
 
-    ScheduleParams spar{o.tile_nnz, o.tile_rows, o.short_max, o.split_len, o.chunk_nnz};
+    const ScheduleParams spar{o.tile_nnz, o.tile_rows, o.short_max, o.split_len, o.chunk_nnz};
+    h->spA = h->spT = spar;
     build_schedule(m, rowptr, spar, L.batched ? inst_row.data() : nullptr, h->A.host);
     build_schedule(n, rpt.data(), spar, L.batched ? inst_col.data() : nullptr, h->T.host);
 
+    // carved sizes: the schedules just built, or the bound over every autotuner candidate
     Plan need = bound_plan(m, n, nnz, o, L.n_inst, L.batched);
-    need.itemsA = (int)h->A.host.items.size();
-    need.itemsT = (int)h->T.host.items.size();
-    need.splitA = (int)h->A.host.splits.size();
-    need.splitT = (int)h->T.host.splits.size();
-    need.slotsA = h->A.host.n_chunk_slots;
-    need.slotsT = h->T.host.n_chunk_slots;
+    if (!o.autotune) {
+        need.itemsA = (int)h->A.host.items.size();
+        need.itemsT = (int)h->T.host.items.size();
+        need.splitA = (int)h->A.host.splits.size();
+        need.splitT = (int)h->T.host.splits.size();
+        need.slotsA = h->A.host.n_chunk_slots;
+        need.slotsT = h->T.host.n_chunk_slots;
+    }
     if (plan_bytes(need) > ws_bytes) {
         delete h;
         return fail(nullptr, HPRLP_EINVAL, "workspace too small: need " +
@@ -641,6 +673,9 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     }
     h->A.rows = (int)m;
     h->T.rows = (int)n;
+    h->capA[0] = need.itemsA; h->capA[1] = need.splitA; h->capA[2] = need.slotsA;
+    h->capT[0] = need.itemsT; h->capT[1] = need.splitT; h->capT[2] = need.slotsT;
+    h->sched_nnz = nnz;
 
     if (L.batched) {
         // batched work is ordered on a stream of the library's own (stream capture needs a
@@ -658,10 +693,22 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     }
     rc = create_device(h, L, rowptr, colidx, val, b, c, l, u, rpt, cit, pos, sc, order,
                        inst_row, inst_col, cst);
+    if (!rc && o.autotune && nnz >= kTuneMinNnz)
+        rc = tune_schedules(h, rowptr, rpt.data(), L.batched ? inst_row.data() : nullptr,
+                            L.batched ? inst_col.data() : nullptr);
     if (rc) {
         g_create_error = h->err;
         hprlp_destroy(h);
         return rc;
+    }
+    if (L.batched) {  // kept to rebuild the schedules over the instances still iterating
+        h->rpA.assign(rowptr, rowptr + m + 1);
+        h->rpT = std::move(rpt);
+        h->inst_row = std::move(inst_row);
+        h->inst_col = std::move(inst_col);
+        h->inst_nnz.assign(L.n_inst, 0);
+        for (int bi = 0; bi < L.n_inst; ++bi)
+            h->inst_nnz[bi] = rowptr[L.row_off[bi + 1]] - rowptr[L.row_off[bi]];
     }
     *out = h;
     return HPRLP_OK;
@@ -700,6 +747,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->reorder = 1;
     o->profile = 0;
     o->verbose = 0;
+    o->autotune = 0;
     resolve_options(*o);
 }
 
@@ -1005,6 +1053,157 @@ double bytes_per_iter(const hprlp_handle *h) {
            5.0 * h->m * svec;
 }
 
+// Per-instance device state of a batched solve at its start: every instance iterates from
+// k = 0 with sigma = sigma0 (lambda is set after the power method).
+int init_batch_state(hprlp_handle *h, double sigma0, double lam) {
+    const int ni = h->n_inst;
+    std::vector<double> sig((size_t)ni, sigma0), lamv((size_t)ni, lam), zeros((size_t)ni, 0.0);
+    std::vector<long long> zl((size_t)ni, 0);
+    std::vector<int> ones((size_t)ni, 1), zi((size_t)ni, 0);
+    const long long kb0 = 0;
+    int rc;
+    if ((rc = upload(h, h->bd.sigma, sig.data(), sig.size())) ||
+        (rc = upload(h, h->bd.lam, lamv.data(), lamv.size())) ||
+        (rc = upload(h, h->bd.merit0, zeros.data(), zeros.size())) ||
+        (rc = upload(h, h->bd.merit_prev, zeros.data(), zeros.size())) ||
+        (rc = upload(h, h->bd.kstart, zl.data(), zl.size())) ||
+        (rc = upload(h, h->bd.kbase, &kb0, 1)) ||
+        (rc = upload(h, h->bd.iters_done, zl.data(), zl.size())) ||
+        (rc = upload(h, h->bd.restarts, zl.data(), zl.size())) ||
+        (rc = upload(h, h->bd.nchecks, zl.data(), zl.size())) ||
+        (rc = upload(h, h->bd.active, ones.data(), ones.size())) ||
+        (rc = upload(h, h->bd.status, zi.data(), zi.size())) ||
+        (rc = upload(h, h->bd.restart_flag, zi.data(), zi.size())))
+        return rc;
+    return HPRLP_OK;
+}
+
+// Upload schedule S as the schedule of A (col = false) or A^T (col = true), with the
+// per-instance slot lists of a batched handle.
+int install_schedule(hprlp_handle *h, bool col, Schedule &&S) {
+    DevMat &M = col ? h->T : h->A;
+    const int *cap = col ? h->capT : h->capA;
+    if ((int)S.items.size() > cap[0] || (int)S.splits.size() > cap[1] || S.n_chunk_slots > cap[2])
+        return fail(h, HPRLP_ESTATE, "schedule exceeds the carved capacity");
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    int rc;
+    if ((rc = upload(h, M.items, S.items.data(), S.items.size())) ||
+        (rc = upload(h, M.splits, S.splits.data(), S.splits.size())))
+        return rc;
+    M.n_items = (int)S.items.size();
+    M.n_split = (int)S.splits.size();
+    M.tile_nnz = S.tile_nnz;
+    M.tile_rows = S.tile_rows;
+    M.host = std::move(S);
+    if (h->batched) {
+        std::vector<int> ptr, slots;
+        build_segments(M.host, h->n_inst, ptr, slots);
+        if ((rc = upload(h, col ? h->bd.segT_ptr : h->bd.segA_ptr, ptr.data(), ptr.size())) ||
+            (rc = upload(h, col ? h->bd.segT_slots : h->bd.segA_slots, slots.data(), slots.size())))
+            return rc;
+    }
+    return HPRLP_OK;
+}
+
+// Mean duration (ms) of one launch of the row pass (col = false) or column pass, over
+// kTuneReps launches after two warm-up launches, bracketed by HIP events.
+int time_pass(hprlp_handle *h, bool col, double *ms) {
+    IterScalars s;
+    fill_scalars(h, s);
+    const BatchArgs ba = batch_args(h, 0);
+    const BatchArgs *pba = h->batched ? &ba : nullptr;
+    const void *vs = cur_set(h);
+    hipEvent_t e0 = pool_event(h, 0), e1 = pool_event(h, 1);
+    if (!e0 || !e1) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
+    for (int i = 0; i < 2 + kTuneReps; ++i) {
+        if (i == 2) HIPCHK(h, hipEventRecord(e0, h->st));
+        const hipError_t e = col ? launch_col_pass(h->prec, false, h->T, vs, s, h->st, nullptr, pba)
+                                 : launch_row_pass(h->prec, false, h->A, vs, s, h->st, nullptr, pba);
+        if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("pass launch: ") + hipGetErrorString(e));
+    }
+    HIPCHK(h, hipEventRecord(e1, h->st));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&t, e0, e1));
+    *ms = (double)t / kTuneReps;
+    return HPRLP_OK;
+}
+
+bool same_schedule(const Schedule &a, const Schedule &b) {
+    return a.items.size() == b.items.size() && a.splits.size() == b.splits.size() &&
+           std::memcmp(a.items.data(), b.items.data(), a.items.size() * sizeof(int4)) == 0 &&
+           std::memcmp(a.splits.data(), b.splits.data(), a.splits.size() * sizeof(int4)) == 0;
+}
+
+// Schedule autotuner: for each matrix, coordinate descent over the candidate table (tile
+// shape, then short_max, then split_len x chunk_nnz when rows are long enough to split),
+// timing the pass of each distinct schedule on the uploaded problem (Halpern state at the
+// origin, sigma = lambda = 1).  A candidate replaces the best one only if it is at least 3%
+// faster.  The chosen schedules stay installed; their parameters are in spA / spT.
+int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
+                   const int32_t *inst_row, const int32_t *inst_col) {
+    int rc;
+    h->prec = h->f32phase ? 1 : (h->mixed ? 2 : 0);
+    h->t = 0;
+    h->sigma = 1.0;
+    h->lambda = 1.0;
+    if ((rc = zero_state(h))) return rc;
+    if (h->batched && (rc = init_batch_state(h, 1.0, 1.0))) return rc;
+    for (int w = 0; w < 2; ++w) {
+        const bool col = w == 1;
+        const int64_t rows = col ? h->n : h->m;
+        const int64_t *rp = col ? rpT : rpA;
+        const int32_t *inst = col ? inst_col : inst_row;
+        ScheduleParams best = col ? h->spT : h->spA;
+        int64_t maxlen = 0;
+        for (int64_t r = 0; r < rows; ++r) maxlen = std::max(maxlen, rp[r + 1] - rp[r]);
+        Schedule cur = (col ? h->T : h->A).host;  // installed at create
+        double best_ms = 0.0;
+        if ((rc = time_pass(h, col, &best_ms))) return rc;
+        Schedule best_s = cur;
+        auto cap_ok = [&](const Schedule &S) {
+            const int *cap = col ? h->capT : h->capA;
+            return (int)S.items.size() <= cap[0] && (int)S.splits.size() <= cap[1] &&
+                   S.n_chunk_slots <= cap[2];
+        };
+        auto try_p = [&](const ScheduleParams &p) -> int {
+            if (p.short_max > p.tile_nnz || p.split_len < p.short_max) return HPRLP_OK;
+            Schedule S;
+            build_schedule(rows, rp, p, inst, S);
+            if (!cap_ok(S) || same_schedule(S, best_s)) return HPRLP_OK;
+            Schedule keep = S;
+            int r2 = install_schedule(h, col, std::move(S));
+            if (r2) return r2;
+            double ms = 0.0;
+            if ((r2 = time_pass(h, col, &ms))) return r2;
+            if (ms < 0.97 * best_ms) {
+                best_ms = ms;
+                best = p;
+                best_s = std::move(keep);
+            }
+            return HPRLP_OK;
+        };
+        for (int tn : kTuneTileNnz)
+            for (int tr : kTuneTileRows)
+                if ((rc = try_p({tn, tr, std::min(best.short_max, tn), best.split_len, best.chunk_nnz})))
+                    return rc;
+        const ScheduleParams shape = best;
+        for (int sm : kTuneShortMax)
+            if ((rc = try_p({shape.tile_nnz, shape.tile_rows, sm, std::max(shape.split_len, sm), shape.chunk_nnz})))
+                return rc;
+        if (maxlen > kTuneMinSplit) {
+            const ScheduleParams sh = best;
+            for (int sl : kTuneSplitLen)
+                for (int ch : kTuneChunk)
+                    if ((rc = try_p({sh.tile_nnz, sh.tile_rows, sh.short_max, sl, ch}))) return rc;
+        }
+        if ((rc = install_schedule(h, col, std::move(best_s)))) return rc;
+        (col ? h->spT : h->spA) = best;
+        h->tuned_ms[w] = best_ms;
+    }
+    return HPRLP_OK;
+}
+
 // ---------------------------------------------------------------------------- one LP
 
 int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) {
@@ -1196,6 +1395,43 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
 
 // ---------------------------------------------------------------------------- a batch
 
+// Rebuild the schedules of A and A^T over the instances with keep[b] != 0 (every instance
+// when keep is empty), upload them with the per-instance slot lists, and drop the captured
+// chunk graphs (they hold the old item counts).  Each instance's work items are the same as
+// in the full schedule (tiles never straddle instances), so the result fits the carved
+// arrays; stopped instances simply have no work item left.
+int set_schedules(hprlp_handle *h, const std::vector<int> &keep) {
+    std::vector<int32_t> ir, ic;
+    int64_t nnz = h->nnz;
+    if (!keep.empty()) {
+        ir = h->inst_row;
+        ic = h->inst_col;
+        for (auto &v : ir) v = keep[v] ? v : -1;
+        for (auto &v : ic) v = keep[v] ? v : -1;
+        nnz = 0;
+        for (int b = 0; b < h->n_inst; ++b)
+            if (keep[b]) nnz += h->inst_nnz[b];
+    }
+    Schedule sa, stt;
+    build_schedule(h->m, h->rpA.data(), h->spA, keep.empty() ? h->inst_row.data() : ir.data(), sa);
+    build_schedule(h->n, h->rpT.data(), h->spT, keep.empty() ? h->inst_col.data() : ic.data(), stt);
+    if ((int)sa.items.size() > h->capA[0] || (int)sa.splits.size() > h->capA[1] ||
+        sa.n_chunk_slots > h->capA[2] || (int)stt.items.size() > h->capT[0] ||
+        (int)stt.splits.size() > h->capT[1] || stt.n_chunk_slots > h->capT[2])
+        return fail(h, HPRLP_ESTATE, "rebuilt schedule exceeds the carved capacity");
+    int rc;
+    if ((rc = install_schedule(h, false, std::move(sa))) || (rc = install_schedule(h, true, std::move(stt))))
+        return rc;
+    for (hipGraphExec_t &g : h->graphs)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    h->sched_nnz = nnz;
+    h->compacted = !keep.empty();
+    return HPRLP_OK;
+}
+
 // Record one chunk of check_every iterations on the library stream: first iteration (keep)
 // + its check sums, plain iterations, last iteration (keep) + check sums, the decisions of
 // every instance, the restart copies, and the iteration counter advance.
@@ -1270,27 +1506,11 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
     h->stats = hprlp_stats_t{};
     h->inst_stats.clear();
     h->prec = h->f32phase ? 1 : (h->mixed ? 2 : 0);
+    h->n_compactions = 0;
     int rc;
+    if (h->compacted && (rc = set_schedules(h, {}))) return rc;
     // every instance iterates from w = 0 with sigma = sigma0; outer loops start at k = 0
-    {
-        std::vector<double> sig((size_t)ni, o.sigma0), zeros((size_t)ni, 0.0);
-        std::vector<long long> zl((size_t)ni, 0);
-        std::vector<int> ones((size_t)ni, 1), zi((size_t)ni, 0);
-        const long long kb0 = 0;
-        if ((rc = upload(h, h->bd.sigma, sig.data(), sig.size())) ||
-            (rc = upload(h, h->bd.lam, zeros.data(), zeros.size())) ||
-            (rc = upload(h, h->bd.merit0, zeros.data(), zeros.size())) ||
-            (rc = upload(h, h->bd.merit_prev, zeros.data(), zeros.size())) ||
-            (rc = upload(h, h->bd.kstart, zl.data(), zl.size())) ||
-            (rc = upload(h, h->bd.kbase, &kb0, 1)) ||
-            (rc = upload(h, h->bd.iters_done, zl.data(), zl.size())) ||
-            (rc = upload(h, h->bd.restarts, zl.data(), zl.size())) ||
-            (rc = upload(h, h->bd.nchecks, zl.data(), zl.size())) ||
-            (rc = upload(h, h->bd.active, ones.data(), ones.size())) ||
-            (rc = upload(h, h->bd.status, zi.data(), zi.size())) ||
-            (rc = upload(h, h->bd.restart_flag, zi.data(), zi.size())))
-            return rc;
-    }
+    if ((rc = init_batch_state(h, o.sigma0, 0.0))) return rc;
     std::vector<double> lam((size_t)ni, o.lambda_override);
     int piters = 0;
     if (!h->lam_given.empty()) lam = h->lam_given;
@@ -1307,6 +1527,7 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
 
     std::vector<double> kkt_hist;
     long long k = 0, iters_fp32 = 0;
+    double prev_active = (double)ni;
     int st_all = HPRLP_UNSOLVED;
     for (;;) {
         hipGraphExec_t ex;
@@ -1317,8 +1538,24 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
         k = (long long)h->pinned[3];
         if (h->prec == 1) iters_fp32 = k;
         if (o.verbose)
-            std::fprintf(stderr, "hprlp batch k=%lld active=%.0f max_kkt=%.2e\n", k, n_active, max_kkt);
+            std::fprintf(stderr, "hprlp batch k=%lld active=%.0f max_kkt=%.2e scheduled_nnz=%lld\n",
+                         k, n_active, max_kkt, (long long)h->sched_nnz);
         if (n_active == 0) break;
+        if (n_active < prev_active) {
+            // drop the stopped instances from the schedules once they hold an eighth of the
+            // scheduled nonzeros (their work items still stream their nonzeros; only the
+            // writes are skipped)
+            std::vector<int> act((size_t)ni);
+            if ((rc = download(h, act.data(), h->bd.active, act.size()))) return rc;
+            int64_t live = 0;
+            for (int b = 0; b < ni; ++b)
+                if (act[b]) live += h->inst_nnz[b];
+            if (live <= (h->sched_nnz * 7) / 8) {
+                if ((rc = set_schedules(h, act))) return rc;
+                h->n_compactions++;
+            }
+            prev_active = n_active;
+        }
         if (k >= o.max_iter) {
             st_all = HPRLP_ITER_LIMIT;
             break;
@@ -1391,6 +1628,7 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
     s.t_solve_ms = t_end - t_start;
     s.bytes_per_iter = bytes_per_iter(h);
     s.n_checks = k / o.check_every;
+    s.n_compactions = h->n_compactions;
     if (status) *status = worst;
     return HPRLP_OK;
 }
@@ -1498,6 +1736,24 @@ extern "C" int hprlp_get_trace_instance(const hprlp_handle *hc, int32_t i, doubl
     return rc;
 }
 
+extern "C" int hprlp_get_schedule(const hprlp_handle *hc, int matrix, int32_t *params,
+                                  int64_t *counts, double *tuned_ms) {
+    hprlp_handle *h = const_cast<hprlp_handle *>(hc);
+    if (!h || (matrix != 0 && matrix != 1)) return fail(h, HPRLP_EINVAL, "bad argument");
+    const ScheduleParams &p = matrix == 0 ? h->spA : h->spT;
+    const Schedule &S = (matrix == 0 ? h->A : h->T).host;
+    if (params) {
+        params[0] = p.tile_nnz; params[1] = p.tile_rows; params[2] = p.short_max;
+        params[3] = p.split_len; params[4] = p.chunk_nnz;
+    }
+    if (counts) {
+        counts[0] = (int64_t)S.items.size(); counts[1] = S.n_tiles; counts[2] = S.n_rowitems;
+        counts[3] = S.n_chunks;
+    }
+    if (tuned_ms) *tuned_ms = h->tuned_ms[matrix];
+    return HPRLP_OK;
+}
+
 extern "C" int hprlp_time_passes(hprlp_handle *h, int reps, double *col_ms, double *row_ms) {
     if (!h || reps < 1) return fail(h, HPRLP_EINVAL, "bad argument");
     if (!h->solved) return fail(h, HPRLP_ESTATE, "call after a solve");
@@ -1510,6 +1766,7 @@ extern "C" int hprlp_time_passes(hprlp_handle *h, int reps, double *col_ms, doub
         std::vector<int> ones((size_t)h->n_inst, 1);
         int rc = upload(h, h->bd.active, ones.data(), ones.size());
         if (rc) return rc;
+        if (h->compacted && (rc = set_schedules(h, {}))) return rc;
     }
     hipEvent_t e[4];
     for (int i = 0; i < 4; ++i) {

@@ -40,6 +40,9 @@ struct ScheduleParams {
     int tile_nnz, tile_rows, short_max, split_len, chunk_nnz;
 };
 
+// inst_of_row (nullable): instance of every row; tiles never straddle instances, and rows
+// with a negative instance are left out of the schedule (batched solves drop the instances
+// that have stopped).
 void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &sp,
                     const int32_t *inst_of_row /* nullable */, Schedule &out);
 

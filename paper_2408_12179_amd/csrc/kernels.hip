@@ -128,6 +128,10 @@ __device__ __forceinline__ PassCtx ctx_batch(const BatchArgs &b, int inst) {
 
 constexpr int kEPT = 8;   // nonzeros per thread per batch (tile_nnz <= kWG * kEPT)
 constexpr int kRPT = 4;   // rows per thread in the tile epilogue (tile_rows <= kWG * kRPT)
+// Epilogue operands are prefetched (issued before the nonzero stream) for the first kPRE rows
+// of each thread only: tiles rarely have more than kWG rows, and holding kRPT rows of operands
+// through the SpMV phases would cost the registers that keep more workgroups resident.
+constexpr int kPRE = 1;
 
 template <class M> struct RawT {
     int j;
@@ -181,20 +185,23 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
 #pragma unroll
     for (int j = 0; j < NQ; ++j) q[j] = 0.0;
 
+    // The loads of a work item are issued before its instance's active flag is known (a
+    // batched solve's scalars come from memory): only the epilogue writes wait for it.
+    // Stopped instances are dropped from the schedules by the host as they accumulate.
     if (kind == IT_TILE) {
         const int r0 = it.x, P0 = it.y, inst = it.z;
         const PassCtx ctx = op.begin(inst);
-        if (ctx.active) {  // uniform over the workgroup
+        {
             S *prod = reinterpret_cast<S *>(smem);
             S *rsum = prod + tile_cap;
             int *rpl = reinterpret_cast<int *>(rsum + rows_cap);
             const int nrows = it.w >> 14, cnt = (it.w >> 2) & 4095;
             const int r1 = r0 + nrows;
-            Pre pre[kRPT];
+            Pre pre[kPRE];
             if constexpr (Op::PREFETCH) {
                 // rows past the tile re-load the tile's last row (valid, unused)
 #pragma unroll
-                for (int u = 0; u < kRPT; ++u) pre[u] = op.load(min(r0 + tid + u * kWG, r1 - 1));
+                for (int u = 0; u < kPRE; ++u) pre[u] = op.load(min(r0 + tid + u * kWG, r1 - 1));
             }
             // the tile's row pointers, staged in LDS for phase 2
             int rpv[kRPT];
@@ -235,29 +242,30 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
 #pragma unroll
             for (int u = 0; u < kRPT; ++u) {
                 const int rr = tid + u * kWG;
-                if (rr < nrows) {
-                    if constexpr (Op::PREFETCH) op.apply(r0 + rr, rsum[rr], pre[u], ctx, q);
-                    else op.apply(r0 + rr, rsum[rr], op.load(r0 + rr), ctx, q);
+                if (rr < nrows && ctx.active) {
+                    if constexpr (Op::PREFETCH) {
+                        if (u < kPRE) op.apply(r0 + rr, rsum[rr], pre[u < kPRE ? u : 0], ctx, q);
+                        else op.apply(r0 + rr, rsum[rr], op.load(r0 + rr), ctx, q);
+                    } else {
+                        op.apply(r0 + rr, rsum[rr], op.load(r0 + rr), ctx, q);
+                    }
                 }
             }
         }
     } else if (kind == IT_ROW) {
         const int r = it.x;
         const PassCtx ctx = op.begin(it.w >> 2);
-        if (ctx.active) {
-            Pre pre{};
-            if (Op::PREFETCH && tid == 0) pre = op.load(r);
-            S s = row_sum(op, it.y, it.z, tid);
-            s = block_sum(s, red);
-            if (tid == 0) op.apply(r, s, Op::PREFETCH ? pre : op.load(r), ctx, q);
-        }
+        Pre pre{};
+        if (Op::PREFETCH && tid == 0) pre = op.load(r);
+        S s = row_sum(op, it.y, it.z, tid);
+        s = block_sum(s, red);
+        if (tid == 0 && ctx.active) op.apply(r, s, Op::PREFETCH ? pre : op.load(r), ctx, q);
     } else if (kind == IT_CHUNK) {
-        const PassCtx ctx = op.begin(it.z);
-        if (ctx.active) {
-            S s = row_sum(op, it.x, it.y, tid);
-            s = block_sum(s, red);
-            if (tid == 0) split_part[it.w >> 2] = s;
-        }
+        // the partial of a stopped instance's chunk is written but never used (its split row
+        // is not finished)
+        S s = row_sum(op, it.x, it.y, tid);
+        s = block_sum(s, red);
+        if (tid == 0) split_part[it.w >> 2] = s;
     }  // IT_EMPTY: padding item, only the (zero) check partials below
     if constexpr (Op::NQ > 0) {
 #pragma unroll

@@ -191,6 +191,11 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
     };
     for (int64_t r = 0; r < rows; ++r) {
         const int64_t len = rowptr[r + 1] - rowptr[r];
+        if (inst(r) < 0) {  // row of an instance left out of this schedule
+            close_tile(r);
+            r0 = r + 1;
+            continue;
+        }
         const bool new_inst = inst_of_row && r > r0 && inst(r) != inst(r0);
         if (len > sp.short_max) {
             close_tile(r);

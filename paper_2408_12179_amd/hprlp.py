@@ -29,8 +29,8 @@ BATCH_TRACE_COLS = ["k", "t", "r", "sigma", "merit", "rel_p", "rel_d", "rel_gap"
 EXPORTS = ["hprlp_default_options", "hprlp_workspace_bytes", "hprlp_workspace_bytes_batched",
            "hprlp_create", "hprlp_create_batched", "hprlp_solve", "hprlp_stats",
            "hprlp_stats_instance", "hprlp_get_iterate", "hprlp_get_trace",
-           "hprlp_get_trace_instance", "hprlp_time_passes", "hprlp_last_error",
-           "hprlp_destroy"]
+           "hprlp_get_trace_instance", "hprlp_get_schedule", "hprlp_time_passes",
+           "hprlp_last_error", "hprlp_destroy"]
 
 
 class Options(C.Structure):
@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("stall_checks", C.c_int), ("tile_nnz", C.c_int),
                 ("tile_rows", C.c_int), ("short_max", C.c_int), ("split_len", C.c_int),
                 ("chunk_nnz", C.c_int), ("reorder", C.c_int), ("profile", C.c_int),
-                ("verbose", C.c_int)]
+                ("verbose", C.c_int), ("autotune", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -58,7 +58,7 @@ class Stats(C.Structure):
                 ("bytes_per_iter", C.c_double), ("col_pass_ms", C.c_double),
                 ("row_pass_ms", C.c_double), ("col_pass_launches", C.c_longlong),
                 ("row_pass_launches", C.c_longlong), ("split_ms", C.c_double),
-                ("n_checks", C.c_longlong)]
+                ("n_checks", C.c_longlong), ("n_compactions", C.c_longlong)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -98,6 +98,7 @@ def load() -> C.CDLL:
     lib.hprlp_stats_instance.argtypes = [P, C.c_int32, C.POINTER(Stats)]
     lib.hprlp_get_trace_instance.argtypes = [P, C.c_int32, P, C.c_longlong,
                                              C.POINTER(C.c_longlong)]
+    lib.hprlp_get_schedule.argtypes = [P, C.c_int, P, P, C.POINTER(C.c_double)]
     lib.hprlp_solve.argtypes = [P, P, P, P, C.POINTER(C.c_int)]
     lib.hprlp_stats.argtypes = [P, C.POINTER(Stats)]
     lib.hprlp_get_iterate.argtypes = [P, C.c_int, P]
@@ -264,6 +265,19 @@ class Solver:
         out = np.zeros((n.value, len(TRACE_COLS)))
         self._check(self._lib.hprlp_get_trace(self._h, _ptr(out), n.value, C.byref(n)))
         return out
+
+    def schedule(self, matrix: int) -> dict:
+        """Schedule of A (matrix=0, row pass) or A^T (matrix=1, column pass)."""
+        params = np.zeros(5, dtype=np.int32)
+        counts = np.zeros(4, dtype=np.int64)
+        ms = C.c_double()
+        self._check(self._lib.hprlp_get_schedule(self._h, matrix, _ptr(params), _ptr(counts),
+                                                 C.byref(ms)))
+        keys = ("tile_nnz", "tile_rows", "short_max", "split_len", "chunk_nnz")
+        d = {k: int(v) for k, v in zip(keys, params)}
+        d.update(items=int(counts[0]), tiles=int(counts[1]), row_items=int(counts[2]),
+                 chunks=int(counts[3]), tuned_ms=ms.value)
+        return d
 
     def time_passes(self, reps: int = 50):
         a, b = C.c_double(), C.c_double()

@@ -223,3 +223,10 @@ def test_workspace_bytes_batched(lib):
     with pytest.raises(hprlp.HPRLPError) as e:
         hprlp.workspace_bytes_batched(500, 400, 800, 4000, o)  # more instances than rows
     assert e.value.code == hprlp.EDIM
+
+
+def test_workspace_covers_autotuner_candidates(lib):
+    o = hprlp.default_options(chunk_nnz=8192, split_len=16384)
+    ot = hprlp.default_options(chunk_nnz=8192, split_len=16384, autotune=1)
+    assert hprlp.workspace_bytes(5000, 5000, 20000, 10**7, ot) > \
+        hprlp.workspace_bytes(5000, 5000, 20000, 10**7, o)
