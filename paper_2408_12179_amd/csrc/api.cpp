@@ -904,6 +904,8 @@ double merit_of(const double *q, double sigma, double lambda) {
     return std::sqrt(v > 0.0 ? v : 0.0);
 }
 
+int set_schedules(hprlp_handle *h, const std::vector<int> &keep);
+
 // Power method (Section 4.1) on every instance at once: v0 = 1/sqrt(m_b) on the rows of
 // instance b; lambda_b is the Rayleigh quotient at the first iteration whose change is
 // <= power_tol relative (or at power_max_iter).  Writes lam[b] and the largest iteration
@@ -957,8 +959,21 @@ int power_method(hprlp_handle *h, std::vector<double> &lam, int *iters) {
                 max_it = std::max(max_it, done[b]);
             }
         }
+        if (h->batched && n_done < ni) {
+            // instances whose lambda is settled leave the schedules once they hold an eighth
+            // of the scheduled nonzeros (the others' iterations are unchanged)
+            int64_t live = 0;
+            for (int b = 0; b < ni; ++b)
+                if (!done[b]) live += h->inst_nnz[b];
+            if (live <= (h->sched_nnz * 7) / 8) {
+                std::vector<int> keep((size_t)ni);
+                for (int b = 0; b < ni; ++b) keep[b] = done[b] ? 0 : 1;
+                if ((rc = set_schedules(h, keep))) return rc;
+            }
+        }
     }
     *iters = max_it;
+    if (h->batched && h->compacted && (rc = set_schedules(h, {}))) return rc;
     return HPRLP_OK;
 }
 
