@@ -126,6 +126,8 @@ typedef struct {
     long long n_checks;
     long long n_compactions; /* batched: times the schedules were rebuilt without the      */
                              /* instances that had stopped                                  */
+    double t_setup_ms;       /* hprlp_create: validation, preconditioning, transpose,       */
+                             /* schedules (and autotuning), upload                          */
 } hprlp_stats_t;
 
 /* Iterates that hprlp_get_iterate can return (original space unless noted). */
@@ -202,6 +204,14 @@ int hprlp_create_batched(hprlp_handle **out, int32_t n_inst, const int64_t *inst
  * The call blocks until the result is ready.  Batched handle: every instance is solved;
  * *status is OPTIMAL only if every instance is, else the first other status met. */
 int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int *status);
+
+/* Run `iters` more iterations of Algorithm 2 (the column and row passes, Section 3.3) from
+ * the current state of a single-LP handle, continuing the current outer loop (t and k
+ * advance) with no check, restart or sigma update: a debugging / parity aid that exposes the
+ * plain fixed-point map.  Needs a previous hprlp_solve on the handle (ESTATE otherwise);
+ * EINVAL on a batched handle or iters < 0.  The returned w_bar (XBAR, YBAR, ZBAR) stays that
+ * of the last check; XCUR / YCUR give the new current iterate.  Blocks until done. */
+int hprlp_step(hprlp_handle *h, int iters);
 
 /* Statistics of the last solve.  Batched handle: iters = iterations run, restarts summed,
  * residuals the largest over the instances, objectives summed; per-instance figures come

@@ -123,6 +123,7 @@ struct hprlp_handle {
     int64_t sched_nnz = 0;                    // nonzeros covered by the current schedules
     bool compacted = false;
     long long n_compactions = 0;
+    double t_setup_ms = 0.0;                  // duration of create
     // solve state (single LP)
     int prec = 0;
     long long t = 0, k = 0, r = 0;
@@ -511,6 +512,7 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
                 const hprlp_options *opt, void *d_workspace, size_t ws_bytes, void *stream) {
     if (!out) return fail(nullptr, HPRLP_EINVAL, "out is null");
     *out = nullptr;
+    const double t_create = now_ms();
     hprlp_options o;
     if (opt) o = *opt;
     else hprlp_default_options(&o);
@@ -710,6 +712,7 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
         for (int bi = 0; bi < L.n_inst; ++bi)
             h->inst_nnz[bi] = rowptr[L.row_off[bi + 1]] - rowptr[L.row_off[bi]];
     }
+    h->t_setup_ms = now_ms() - t_create;
     *out = h;
     return HPRLP_OK;
 }
@@ -1404,6 +1407,7 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
     s.row_pass_launches = prof_n[1];
     s.split_ms = split_ms;
     s.n_checks = (long long)h->trace.size();
+    s.t_setup_ms = h->t_setup_ms;
     if (status) *status = st_out;
     return HPRLP_OK;
 }
@@ -1644,6 +1648,7 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
     s.bytes_per_iter = bytes_per_iter(h);
     s.n_checks = k / o.check_every;
     s.n_compactions = h->n_compactions;
+    s.t_setup_ms = h->t_setup_ms;
     if (status) *status = worst;
     return HPRLP_OK;
 }
@@ -1766,6 +1771,20 @@ extern "C" int hprlp_get_schedule(const hprlp_handle *hc, int matrix, int32_t *p
         counts[3] = S.n_chunks;
     }
     if (tuned_ms) *tuned_ms = h->tuned_ms[matrix];
+    return HPRLP_OK;
+}
+
+extern "C" int hprlp_step(hprlp_handle *h, int iters) {
+    if (!h || iters < 0) return fail(h, HPRLP_EINVAL, "bad argument");
+    if (h->batched) return fail(h, HPRLP_EINVAL, "hprlp_step is for single-LP handles");
+    if (!h->solved) return fail(h, HPRLP_ESTATE, "call after a solve");
+    size_t ev = 0;
+    for (int i = 0; i < iters; ++i) {
+        const int rc = run_iteration(h, false, nullptr, &ev);
+        if (rc) return rc;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->stats.iters = h->k;
     return HPRLP_OK;
 }
 

@@ -29,8 +29,8 @@ BATCH_TRACE_COLS = ["k", "t", "r", "sigma", "merit", "rel_p", "rel_d", "rel_gap"
 EXPORTS = ["hprlp_default_options", "hprlp_workspace_bytes", "hprlp_workspace_bytes_batched",
            "hprlp_create", "hprlp_create_batched", "hprlp_solve", "hprlp_stats",
            "hprlp_stats_instance", "hprlp_get_iterate", "hprlp_get_trace",
-           "hprlp_get_trace_instance", "hprlp_get_schedule", "hprlp_time_passes",
-           "hprlp_last_error", "hprlp_destroy"]
+           "hprlp_get_trace_instance", "hprlp_get_schedule", "hprlp_step",
+           "hprlp_time_passes", "hprlp_last_error", "hprlp_destroy"]
 
 
 class Options(C.Structure):
@@ -58,7 +58,8 @@ class Stats(C.Structure):
                 ("bytes_per_iter", C.c_double), ("col_pass_ms", C.c_double),
                 ("row_pass_ms", C.c_double), ("col_pass_launches", C.c_longlong),
                 ("row_pass_launches", C.c_longlong), ("split_ms", C.c_double),
-                ("n_checks", C.c_longlong), ("n_compactions", C.c_longlong)]
+                ("n_checks", C.c_longlong), ("n_compactions", C.c_longlong),
+                ("t_setup_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -100,6 +101,7 @@ def load() -> C.CDLL:
                                              C.POINTER(C.c_longlong)]
     lib.hprlp_get_schedule.argtypes = [P, C.c_int, P, P, C.POINTER(C.c_double)]
     lib.hprlp_solve.argtypes = [P, P, P, P, C.POINTER(C.c_int)]
+    lib.hprlp_step.argtypes = [P, C.c_int]
     lib.hprlp_stats.argtypes = [P, C.POINTER(Stats)]
     lib.hprlp_get_iterate.argtypes = [P, C.c_int, P]
     lib.hprlp_get_trace.argtypes = [P, P, C.c_longlong, C.POINTER(C.c_longlong)]
@@ -278,6 +280,10 @@ class Solver:
         d.update(items=int(counts[0]), tiles=int(counts[1]), row_items=int(counts[2]),
                  chunks=int(counts[3]), tuned_ms=ms.value)
         return d
+
+    def step(self, iters: int):
+        """Run `iters` plain iterations (no checks) from the current state (after a solve)."""
+        self._check(self._lib.hprlp_step(self._h, iters))
 
     def time_passes(self, reps: int = 50):
         a, b = C.c_double(), C.c_double()

@@ -230,3 +230,8 @@ def test_workspace_covers_autotuner_candidates(lib):
     ot = hprlp.default_options(chunk_nnz=8192, split_len=16384, autotune=1)
     assert hprlp.workspace_bytes(5000, 5000, 20000, 10**7, ot) > \
         hprlp.workspace_bytes(5000, 5000, 20000, 10**7, o)
+
+
+def test_step_rejects_null_handle(lib):
+    assert lib.hprlp_step(None, 10) == hprlp.EINVAL
+    assert lib.hprlp_last_error(None)

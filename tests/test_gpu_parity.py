@@ -157,3 +157,20 @@ def test_edge_cases_parity(case):
         assert rel(s.iterate(hprlp.YCUR), ref.y_cur) <= 1e-10, (case, sched)
         assert rel(sol.x, ref.x) <= 1e-10 and rel(sol.y, ref.y) <= 1e-10
         s.close()
+
+
+def test_step_continues_the_iteration():
+    # 100 iterations (a check at the last one, no restart before k = 150), then 50 plain
+    # iterations: the same current iterate as a 150-iteration solve and as the oracle's
+    lp = lpgen.make("tiny")
+    ref = oracle.solve(lp, max_iter=150)
+    a = hprlp.Solver(lp, max_iter=100, lambda_override=ref.lam)
+    a.solve()
+    a.step(50)
+    assert a.stats()["iters"] == 150
+    b = hprlp.Solver(lp, max_iter=150, lambda_override=ref.lam)
+    b.solve()
+    for which, r in ((hprlp.XCUR, ref.x_cur), (hprlp.YCUR, ref.y_cur)):
+        assert rel(a.iterate(which), b.iterate(which)) <= 1e-14
+        assert rel(a.iterate(which), r) <= 1e-10
+    assert b.stats()["t_setup_ms"] > 0
