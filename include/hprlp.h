@@ -88,7 +88,7 @@ typedef struct {
     int precision;           /* hprlp_precision (default HPRLP_FP64)                       */
     double tol_switch;       /* MIXED: switch to FP64 once rel. KKT <= this (default 1e-5) */
     int stall_checks;        /* MIXED: also switch when the best rel. KKT of the FP32 phase */
-                             /* has not halved over this many checks (default 10; 0: off)  */
+                             /* has not halved over this many checks (default 6; 0: off)   */
     int tile_nnz;            /* schedule: nonzeros staged per tile (0 = default)           */
     int tile_rows;           /* schedule: rows per tile (0 = default)                      */
     int short_max;           /* schedule: longest row kept in tiles (0 = default)          */

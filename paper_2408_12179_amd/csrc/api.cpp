@@ -746,7 +746,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->sigma_update = 1;
     o->precision = HPRLP_FP64;
     o->tol_switch = 1e-5;
-    o->stall_checks = 10;
+    o->stall_checks = 6;
     o->reorder = 1;
     o->profile = 0;
     o->verbose = 0;
