@@ -1,0 +1,74 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times
+(schedules picked by the autotuner, batch256 with check_every = 100).
+
+The oracle runs the same iterations on the CPU (about 29 iterations/s on zipf1m on one
+core), so the first 100 iterations are compared element by element.  Both sides use
+lambda = 1: after the Pock-Chambolle pass lambda_1(A~ A~^T) <= 1 (pinned by the oracle
+tests), so 1 is a valid lambda of the method, and the oracle's power method at these
+sizes would take minutes.  The mixed-precision workloads are checked on their FP64-phase
+kernels (FP32 A, FP64 vectors), which give FP64 iterates.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from paper_2408_12179_amd import hprlp
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def _single(name, iters, precision):
+    lp = lpgen.make(name)
+    ref = oracle.solve(lp, max_iter=iters, lambda_override=1.0)
+    s = hprlp.Solver(lp, max_iter=iters, lambda_override=1.0, autotune=1, precision=precision)
+    sol = s.solve()
+    assert sol.stats["iters"] == ref.iters == iters
+    out = dict(x_bar=rel(sol.x, ref.x), y_bar=rel(sol.y, ref.y), z_bar=rel(sol.z, ref.z),
+               x_cur=rel(s.iterate(hprlp.XCUR), ref.x_cur),
+               y_cur=rel(s.iterate(hprlp.YCUR), ref.y_cur))
+    print(name, s.schedule(0), s.schedule(1), {k: f"{v:.2e}" for k, v in out.items()})
+    for k, v in out.items():
+        assert v <= 1e-10, (name, k, v)
+    # a sample of single entries, relative to the vector's scale
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, lp.n, 1000)
+    assert np.max(np.abs(sol.x[idx] - ref.x[idx])) <= 1e-10 * max(np.max(np.abs(ref.x)), 1.0)
+    s.close()
+
+
+def test_fullsize_zipf1m_fp64():
+    _single("zipf1m", 100, hprlp.FP64)
+
+
+def test_fullsize_transport10m_fp64_phase_kernels():
+    _single("transport10m", 50, hprlp.FP64_A32)
+
+
+def test_fullsize_zipf4m_fp64_phase_kernels():
+    _single("zipf4m", 30, hprlp.FP64_A32)
+
+
+def test_fullsize_batch256_sampled_instances():
+    lp = lpgen.make("batch256")
+    n_inst = len(lp.inst_m1)
+    iters = 200
+    s = hprlp.Solver(lp, batched=True, lambdas=np.ones(n_inst), max_iter=iters,
+                     check_every=100, autotune=1)
+    sol = s.solve()
+    for i in (0, 117, n_inst - 1):
+        inst = lp.instance(i)
+        ref = oracle.solve(inst, max_iter=iters, check_every=100, lambda_override=1.0)
+        st = s.stats_instance(i)
+        assert st["iters"] == ref.iters and st["restarts"] == ref.restarts, (i, st, ref.iters)
+        r0, r1 = lp.inst_row_off[i], lp.inst_row_off[i + 1]
+        c0, c1 = lp.inst_col_off[i], lp.inst_col_off[i + 1]
+        ex, ey, ez = rel(sol.x[c0:c1], ref.x), rel(sol.y[r0:r1], ref.y), rel(sol.z[c0:c1], ref.z)
+        print("batch256 instance", i, inst.m, inst.n, f"{ex:.2e} {ey:.2e} {ez:.2e}")
+        assert max(ex, ey, ez) <= 1e-10, (i, ex, ey, ez)
+    s.close()
