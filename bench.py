@@ -58,7 +58,7 @@ def read_traffic(kind, workload):
     return float(mt.group(1)) if mt else None
 
 
-def cpu_baseline(lp, gpu_iters, gpu_power_iters, sample_iters=60, sample_power=20):
+def cpu_baseline(lp, gpu_iters, gpu_power_iters, sample_iters=300, sample_power=60):
     """The oracle (plain FP64 C, one thread) timed on a bounded sample of the same workload:
     sample_power power iterations and sample_iters HPR-LP iterations, extrapolated to the
     GPU run's counts."""
@@ -77,8 +77,8 @@ def cpu_baseline(lp, gpu_iters, gpu_power_iters, sample_iters=60, sample_power=2
             "oracle_iters_per_s": it_rate}
 
 
-def cpu_baseline_batched(lp, inst_iters, power_iters, n_sample=4, sample_iters=40,
-                         sample_power=10):
+def cpu_baseline_batched(lp, inst_iters, power_iters, n_sample=16, sample_iters=800,
+                         sample_power=100):
     """The oracle on n_sample instances spread over the batch (sample_power power and
     sample_iters HPR-LP iterations each); its cost per nonzero-iteration, applied to every
     instance's own iteration count in the GPU run (and the power iterations)."""

@@ -179,3 +179,21 @@ def test_batched_deterministic_and_resolvable():
     b = s.solve()  # the graphs are reused; state is re-initialised by every solve
     assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y)
     assert a.stats["iters"] == b.stats["iters"]
+
+
+def test_batched_many_small_instances():
+    # more instances than the decision kernel's 1024 threads and more reduction workgroups:
+    # every instance must stop where the oracle stops; a sample is compared element-wise
+    lp = lpgen.batched_lp(1500, m_range=(4, 12), rho_range=(2.0, 4.0), name="many")
+    n_inst = len(lp.inst_m1)
+    s = hprlp.Solver(lp, batched=True, lambdas=np.ones(n_inst), max_iter=2000, check_every=CE)
+    sol = s.solve()
+    for i in (0, 1023, 1024, 1499):
+        ref = oracle.solve(lp.instance(i), max_iter=2000, check_every=CE, lambda_override=1.0)
+        st = s.stats_instance(i)
+        assert st["iters"] == ref.iters and st["status"] == ref.status, (i, st["iters"], ref.iters)
+        x, y, z = _instance_outputs(sol, lp, i)
+        assert rel(x, ref.x) <= 1e-10 and rel(y, ref.y) <= 1e-10, i
+    print("many: statuses", {k: sum(s.stats_instance(i)["status"] == k for i in range(n_inst))
+                             for k in ("OPTIMAL", "ITER_LIMIT")}, "compactions",
+          sol.stats["n_compactions"])

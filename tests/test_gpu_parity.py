@@ -174,3 +174,17 @@ def test_step_continues_the_iteration():
         assert rel(a.iterate(which), b.iterate(which)) <= 1e-14
         assert rel(a.iterate(which), r) <= 1e-10
     assert b.stats()["t_setup_ms"] > 0
+
+
+def test_infeasible_lp_runs_to_the_iteration_limit():
+    # x1 + x2 = 3 with 0 <= x <= 1 has no feasible point and the method has no infeasibility
+    # detection: both sides run to the limit with the same iterates and a large residual
+    lp = lpgen.LP("infeasible", 1, 0, 2, np.array([0, 2], dtype=np.int64),
+                  np.array([0, 1], dtype=np.int32), np.array([1.0, 1.0]), np.array([3.0]),
+                  np.array([1.0, 2.0]), np.zeros(2), np.ones(2))
+    ref = oracle.solve(lp, max_iter=3000)
+    s = hprlp.Solver(lp, max_iter=3000, lambda_override=ref.lam)
+    sol = s.solve()
+    assert ref.status == sol.status == "ITER_LIMIT"
+    assert sol.stats["rel_p"] > 1e-3 and np.all(np.isfinite(sol.x)) and np.all(np.isfinite(sol.y))
+    assert rel(sol.x, ref.x) <= 1e-10
