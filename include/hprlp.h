@@ -88,7 +88,8 @@ typedef struct {
     int precision;           /* hprlp_precision (default HPRLP_FP64)                       */
     double tol_switch;       /* MIXED: switch to FP64 once rel. KKT <= this (default 1e-5) */
     int stall_checks;        /* MIXED: also switch when the best rel. KKT of the FP32 phase */
-                             /* has not halved over this many checks (default 6; 0: off)   */
+                             /* has not fallen below stall_ratio x its earlier best over   */
+                             /* this many checks (default 6; 0: off)                       */
     int tile_nnz;            /* schedule: nonzeros staged per tile (0 = default)           */
     int tile_rows;           /* schedule: rows per tile (0 = default)                      */
     int short_max;           /* schedule: longest row kept in tiles (0 = default)          */
@@ -104,6 +105,9 @@ typedef struct {
                              /* uploaded problem and keep the fastest per matrix (problems  */
                              /* with >= 1e5 nonzeros); the schedule fields above are then   */
                              /* the starting point.  0 (default): use them as given         */
+    double stall_ratio;      /* MIXED stall rule: switch when the best rel. KKT of the last */
+                             /* stall_checks checks is above stall_ratio x the best before */
+                             /* them (default 0.5; in (0, 1])                               */
 } hprlp_options;
 
 typedef struct {

@@ -751,6 +751,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->profile = 0;
     o->verbose = 0;
     o->autotune = 0;
+    o->stall_ratio = 0.5;
     resolve_options(*o);
 }
 
@@ -1370,15 +1371,15 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
         h->trace.push_back(row);
         if (h->prec == 1) {
             // switch to FP64 at tol_switch, or when FP32 rounding stalls the iteration: the
-            // best residual of the last stall_checks checks is not below half of the best
-            // one before them
+            // best residual of the last stall_checks checks is not below stall_ratio times
+            // the best one before them
             bool sw = kkt <= o.tol_switch;
             kkt_hist.push_back(kkt);
             const size_t S = (size_t)o.stall_checks, H = kkt_hist.size();
             if (!sw && S > 0 && H > S) {
                 const double before = *std::min_element(kkt_hist.begin(), kkt_hist.end() - S);
                 const double recent = *std::min_element(kkt_hist.end() - S, kkt_hist.end());
-                sw = recent > 0.5 * before;
+                sw = recent > o.stall_ratio * before;
             }
             if (sw && (rc = promote(h))) return rc;
         }
@@ -1591,7 +1592,7 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
             if (!sw && S > 0 && H > S) {
                 const double before = *std::min_element(kkt_hist.begin(), kkt_hist.end() - S);
                 const double recent = *std::min_element(kkt_hist.end() - S, kkt_hist.end());
-                sw = recent > 0.5 * before;
+                sw = recent > o.stall_ratio * before;
             }
             if (sw && (rc = promote(h))) return rc;
         }

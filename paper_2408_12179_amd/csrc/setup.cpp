@@ -93,7 +93,8 @@ int validate_options(const hprlp_options &o, std::string &err) {
               o.tile_nnz >= 256 && o.tile_nnz <= kMaxTileNnz && o.tile_rows >= 1 &&
               o.tile_rows <= kMaxTileRows &&
               o.short_max >= 1 && o.short_max <= o.tile_nnz &&
-              o.split_len >= o.short_max && o.chunk_nnz >= 256;
+              o.split_len >= o.short_max && o.chunk_nnz >= 256 && o.stall_ratio > 0 &&
+              o.stall_ratio <= 1;
     if (!ok) err = "invalid option value";
     return ok ? HPRLP_OK : HPRLP_EINVAL;
 }
@@ -104,6 +105,7 @@ void resolve_options(hprlp_options &o) {
     if (o.short_max <= 0) o.short_max = 256;
     if (o.split_len <= 0) o.split_len = 8192;
     if (o.chunk_nnz <= 0) o.chunk_nnz = 4096;
+    if (o.stall_ratio == 0) o.stall_ratio = 0.5;
 }
 
 // Transpose of a CSR matrix by counting sort over the column index.  pos[q] is the position
