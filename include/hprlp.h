@@ -108,6 +108,10 @@ typedef struct {
     double stall_ratio;      /* MIXED stall rule: switch when the best rel. KKT of the last */
                              /* stall_checks checks is above stall_ratio x the best before */
                              /* them (default 0.5; in (0, 1])                               */
+    int graph;               /* single LP: run the plain iterations between two checks as   */
+                             /* one captured hipGraph (identical iterates; needs            */
+                             /* check_every >= 3 and profile = 0).  1 (default): when nnz   */
+                             /* < 2e6 (launch-bound passes); 2: always; 0: never             */
 } hprlp_options;
 
 typedef struct {

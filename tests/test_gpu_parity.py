@@ -188,3 +188,20 @@ def test_infeasible_lp_runs_to_the_iteration_limit():
     assert ref.status == sol.status == "ITER_LIMIT"
     assert sol.stats["rel_p"] > 1e-3 and np.all(np.isfinite(sol.x)) and np.all(np.isfinite(sol.y))
     assert rel(sol.x, ref.x) <= 1e-10
+
+
+@pytest.mark.parametrize("name,scale,prec", [("tiny", 1, hprlp.FP64), ("zipf1m", 0.004, hprlp.FP64),
+                                             ("transport10m", 0.01, hprlp.MIXED)])
+def test_chunk_graphs_are_bitwise_identical(name, scale, prec):
+    # plain iterations as captured graphs (device-resident scalars) against one launch per pass,
+    # over several checks, restarts and (MIXED) the precision switch
+    lp = lpgen.make(name, scale)
+    kw = dict(max_iter=1000, precision=prec, lambda_override=0.9, stall_checks=2)
+    a = hprlp.Solver(lp, graph=2, **kw)
+    sa = a.solve()
+    b = hprlp.Solver(lp, graph=0, **kw)
+    sb = b.solve()
+    assert np.array_equal(sa.x, sb.x) and np.array_equal(sa.y, sb.y) and np.array_equal(sa.z, sb.z)
+    assert np.array_equal(a.iterate(hprlp.XCUR), b.iterate(hprlp.XCUR))
+    assert np.array_equal(a.trace(), b.trace())
+    assert sa.stats["restarts"] >= 1
