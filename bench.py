@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time pass launches with HIP events (default: every 50th "
-                         "iteration of a single-LP solve with >= 2e6 nonzeros is bracketed "
+                         "iteration of a single-LP solve with >= 1e5 nonzeros is bracketed "
                          "by events)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -146,8 +146,8 @@ def main():
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     P = {"mixed": hprlp.MIXED, "fp64a32": hprlp.FP64_A32}.get(prec, hprlp.FP64)
     # HIP events around sampled pass launches inside the timed solve, except where the solve
-    # runs as captured graphs (batches, and single LPs under 2e6 nonzeros: launch-bound)
-    sampled = not (args.no_profile or batched or lp.nnz < 2_000_000)
+    # runs as captured graphs (batches, and single LPs under 1e5 nonzeros: launch-bound)
+    sampled = not (args.no_profile or batched or lp.nnz < 100_000)
     opts = dict(tol=args.tol, time_limit=args.time_limit, precision=P, check_every=ce,
                 profile=50 if sampled else 0, autotune=0 if args.no_autotune else 1)
     t0 = time.perf_counter()

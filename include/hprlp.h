@@ -111,7 +111,7 @@ typedef struct {
     int graph;               /* single LP: run the plain iterations between two checks as   */
                              /* one captured hipGraph (identical iterates; needs            */
                              /* check_every >= 3 and profile = 0).  1 (default): when nnz   */
-                             /* < 2e6 (launch-bound passes); 2: always; 0: never             */
+                             /* < 1e5 (launch-bound passes); 2: always; 0: never             */
 } hprlp_options;
 
 typedef struct {

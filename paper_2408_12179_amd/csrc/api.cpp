@@ -1281,9 +1281,10 @@ int single_graph(hprlp_handle *h, int prec, int len, hipGraphExec_t *out) {
 }
 
 // Below this many nonzeros a single LP's passes are launch-bound and the chunk graphs pay
-// (measured: 8.6 -> 6.9 us per iteration at 1e3 nonzeros); above, the launches are hidden
-// behind the kernels and the instance-scalar kernels cost ~4% (zipf1m, 1.1e7 nonzeros).
-constexpr int64_t kGraphMaxNnz = 2000000;
+// (measured: 8.6 -> 6.9 us per iteration at 1e3 nonzeros); at 1e6 nonzeros the launches
+// are already hidden behind the kernels and the instance-scalar kernels cost more than they
+// save (14.0 -> 15.2 us per iteration; zipf1m, 1.1e7 nonzeros: +4%).
+constexpr int64_t kGraphMaxNnz = 100000;
 
 // Run `count` plain iterations of one LP, whole chunks through the captured graph.
 int run_plain(hprlp_handle *h, long long count) {
