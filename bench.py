@@ -18,6 +18,10 @@ U{5..40}; Zipf(1.1) column popularity; plain FP64).  --config selects the other 
 --compare adds the plain-FP64 GPU solver on the same instances under the same time budget:
 the FP64 single-LP solve for the mixed-precision workloads, and for batch256 the single-LP
 FP64 solver run on the instances one after another.
+--ablation instead runs the four steps of the paper's ablation (Section 4.2, Fig. 1: DR;
++ restart and Halpern; + sigma update; + relaxation rho = 2, i.e. HPR-LP) on the first 64
+batch256 instances, each variant as one batched solve capped at --time-limit, and prints one
+JSON line with the solved counts and shifted geometric means of the iteration counts.
 """
 import argparse
 import json
@@ -106,6 +110,42 @@ def cpu_baseline_batched(lp, inst_iters, power_iters, n_sample=16, sample_iters=
                       f"instance's iteration count in the GPU run"}
 
 
+ABLATION = [
+    ("DR", dict(rho=1.0, use_halpern=0, use_restart=0, sigma_update=0)),
+    ("+ restart, Halpern", dict(rho=1.0, use_halpern=1, use_restart=1, sigma_update=0)),
+    ("+ sigma update", dict(rho=1.0, use_halpern=1, use_restart=1, sigma_update=1)),
+    ("+ relaxation rho = 2 (HPR-LP)", dict(rho=2.0, use_halpern=1, use_restart=1, sigma_update=1)),
+]
+
+
+def ablation(args):
+    """The ablation steps on the first 64 batch256 instances (same seeds and size range)."""
+    import numpy as np
+    import lpgen
+    from paper_2408_12179_amd import hprlp
+    lp = lpgen.batched_lp(64, m_range=(1000, 50000), name="batch256[:64]")
+    rows = []
+    for name, kw in ABLATION:
+        s = hprlp.Solver(lp, batched=True, check_every=100, tol=args.tol,
+                         time_limit=args.time_limit, autotune=1, **kw)
+        t0 = time.perf_counter()
+        sol = s.solve()
+        wall = time.perf_counter() - t0
+        per = [s.stats_instance(i) for i in range(len(lp.inst_m1))]
+        solved = [p["status"] == "OPTIMAL" for p in per]
+        its = np.array([p["iters"] for p in per], dtype=float)
+        sgm = float(np.exp(np.mean(np.log(its + 10.0))) - 10.0)  # unsolved: iterations run
+        rows.append({"variant": name, **kw, "solved": int(sum(solved)),
+                     "instances": len(per), "sgm10_iters": sgm, "wall_s": wall,
+                     "batch_iters": int(sol.stats["iters"])})
+        print(f"[bench] ablation {name}: {sum(solved)}/{len(per)} solved, SGM10 iterations "
+              f"{sgm:.0f}, {wall:.1f} s", file=sys.stderr, flush=True)
+        s.close()
+    print(json.dumps({"ablation": rows, "workload": "first 64 batch256 instances",
+                      "tol": args.tol, "time_limit_s": args.time_limit,
+                      "note": "unsolved instances count with the iterations run"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +159,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--compare", action="store_true",
                     help="also run the plain-FP64 GPU solver on the same instances")
+    ap.add_argument("--ablation", action="store_true",
+                    help="run the ablation steps of Section 4.2 instead of the benchmark")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time pass launches with HIP events (default: every 50th "
@@ -137,6 +179,9 @@ def main():
     import lpgen
     from paper_2408_12179_amd import hprlp
 
+    if args.ablation:
+        ablation(args)
+        return
     batched = args.config == "batch256"
     prec = args.precision or {"zipf4m": "mixed", "transport10m": "mixed"}.get(args.config, "fp64")
     ce = 100 if batched else 150

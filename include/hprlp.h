@@ -112,6 +112,9 @@ typedef struct {
                              /* one captured hipGraph (identical iterates; needs            */
                              /* check_every >= 3 and profile = 0).  1 (default): when nnz   */
                              /* < 1e5 (launch-bound passes); 2: always; 0: never             */
+    double rho;              /* relaxation of Algorithm 2: w_hat = rho w_bar + (1-rho) w,   */
+                             /* in (0, 2]; 2 (default) = Peaceman-Rachford (HPR), 1 =        */
+                             /* Douglas-Rachford (the paper's ablation, Section 4.2)         */
 } hprlp_options;
 
 typedef struct {

@@ -155,6 +155,7 @@ int fail(hprlp_handle *h, int code, const std::string &msg) {
 struct Plan {
     int64_t m, n, nnz;
     bool mixed, f32phase;
+    bool relax = false;  // rho != 2: a relaxed-x vector per precision set
     int itemsA, itemsT, splitA, splitT, slotsA, slotsT;
     int power_cap;
     int n_inst;
@@ -183,6 +184,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     d.xbar = cv.arr<double>(n); d.zint = cv.arr<double>(n); d.dx = cv.arr<double>(n);
     d.y = cv.arr<double>(m); d.y0 = cv.arr<double>(m); d.bd = cv.arr<double>(m);
     d.ybar = cv.arr<double>(m); d.dy = cv.arr<double>(m);
+    if (p.relax) d.xrel = cv.arr<double>(n);
     VecSet<float> f;
     if (p.mixed) {
         d.sc = cv.arr<double>(n);
@@ -194,6 +196,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         f.xbar = cv.arr<float>(n); f.zint = cv.arr<float>(n); f.dx = cv.arr<float>(n);
         f.y = cv.arr<float>(m); f.y0 = cv.arr<float>(m); f.bd = cv.arr<float>(m);
         f.sr = cv.arr<float>(m); f.ybar = cv.arr<float>(m); f.dy = cv.arr<float>(m);
+        if (p.relax) f.xrel = cv.arr<float>(n);
     }
     CheckData c;
     c.ro = cv.arr<double>(m); c.rs = cv.arr<double>(m); c.ys = cv.arr<double>(m);
@@ -271,6 +274,7 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n
     Plan p;
     p.m = m; p.n = n; p.nnz = nnz; p.mixed = o.precision != HPRLP_FP64;
     p.f32phase = o.precision == HPRLP_MIXED;
+    p.relax = o.rho != 2.0;
     // with the autotuner on, room for every candidate schedule (smallest chunk and split)
     const int chunk = o.autotune ? std::min(o.chunk_nnz, kTuneMinChunk) : o.chunk_nnz;
     const int split = o.autotune ? std::min(o.split_len, kTuneMinSplit) : o.split_len;
@@ -770,6 +774,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->autotune = 0;
     o->stall_ratio = 0.5;
     o->graph = 1;
+    o->rho = 2.0;
     resolve_options(*o);
 }
 
@@ -857,6 +862,7 @@ void fill_scalars(const hprlp_handle *h, IterScalars &s) {
         s.hx0 = 0.0; s.hx1 = 1.0; s.hy0 = 0.0; s.hy1 = 1.0;
     }
     s.m1 = h->m1;
+    s.rho = h->opt.rho;
 }
 
 const void *cur_set(const hprlp_handle *h) {
@@ -874,6 +880,7 @@ BatchArgs batch_args(const hprlp_handle *h, int iter_off) {
     a.inv_norm = h->bd.inv_norm;
     a.iter_off = iter_off;
     a.halpern = h->opt.use_halpern;
+    a.rho = h->opt.rho;
     return a;
 }
 
@@ -1003,13 +1010,13 @@ int zero_state(hprlp_handle *h) {
     const long long n = h->n, m = h->m;
     hipError_t e = hipSuccess;
     if (h->prec == 1) {
-        for (float *p : {h->v32.xhat, h->v32.x0})
-            if (e == hipSuccess) e = launch_fill_f(p, n, 0.f, h->st);
+        for (float *p : {h->v32.xhat, h->v32.x0, h->v32.xrel})
+            if (p && e == hipSuccess) e = launch_fill_f(p, n, 0.f, h->st);
         for (float *p : {h->v32.y, h->v32.y0})
             if (e == hipSuccess) e = launch_fill_f(p, m, 0.f, h->st);
     } else {
-        for (double *p : {h->v64.xhat, h->v64.x0})
-            if (e == hipSuccess) e = launch_fill(p, n, 0.0, h->st);
+        for (double *p : {h->v64.xhat, h->v64.x0, h->v64.xrel})
+            if (p && e == hipSuccess) e = launch_fill(p, n, 0.0, h->st);
         for (double *p : {h->v64.y, h->v64.y0})
             if (e == hipSuccess) e = launch_fill(p, m, 0.0, h->st);
     }
@@ -1024,11 +1031,13 @@ int restart_copy(hprlp_handle *h) {
     if (h->prec == 1) {
         e = launch_copy_f(h->v32.x0, h->v32.xbar, n, h->st);
         if (e == hipSuccess) e = launch_copy_f(h->v32.xhat, h->v32.xbar, n, h->st);
+        if (e == hipSuccess && h->v32.xrel) e = launch_copy_f(h->v32.xrel, h->v32.xbar, n, h->st);
         if (e == hipSuccess) e = launch_copy_f(h->v32.y0, h->v32.ybar, m, h->st);
         if (e == hipSuccess) e = launch_copy_f(h->v32.y, h->v32.ybar, m, h->st);
     } else {
         e = launch_copy_d(h->v64.x0, h->v64.xbar, n, h->st);
         if (e == hipSuccess) e = launch_copy_d(h->v64.xhat, h->v64.xbar, n, h->st);
+        if (e == hipSuccess && h->v64.xrel) e = launch_copy_d(h->v64.xrel, h->v64.xbar, n, h->st);
         if (e == hipSuccess) e = launch_copy_d(h->v64.y0, h->v64.ybar, m, h->st);
         if (e == hipSuccess) e = launch_copy_d(h->v64.y, h->v64.ybar, m, h->st);
     }
@@ -1051,6 +1060,7 @@ int promote(hprlp_handle *h) {
                                                 {h->v64.dy, h->v32.dy}};
     for (auto &p : xs)
         if (e == hipSuccess) e = launch_f2d(p.first, p.second, n, h->st);
+    if (e == hipSuccess && h->v64.xrel) e = launch_f2d(h->v64.xrel, h->v32.xrel, n, h->st);
     for (auto &p : ys)
         if (e == hipSuccess) e = launch_f2d(p.first, p.second, m, h->st);
     if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
@@ -1809,7 +1819,9 @@ extern "C" int hprlp_get_iterate(const hprlp_handle *hc, int which, double *out)
         IterScalars s;
         fill_scalars(h, s);
         e = launch_xcur_out(tmp, f32 ? (const void *)h->v32.x0 : h->v64.x0,
-                            f32 ? (const void *)h->v32.xhat : h->v64.xhat, f32, s.hx0, s.hx1,
+                            f32 ? (const void *)(h->v32.xrel ? h->v32.xrel : h->v32.xhat)
+                                : (h->v64.xrel ? h->v64.xrel : h->v64.xhat),
+                            f32, s.hx0, s.hx1,
                             h->ux, 0, h->cperm, h->n, h->st);
         len = h->n;
         break;

@@ -68,6 +68,10 @@ struct DevMat {
 template <class V> struct VecSet {
     V *xhat = nullptr, *x0 = nullptr, *cd = nullptr, *ld = nullptr, *ud = nullptr,
       *sc = nullptr;
+    // relaxation rho != 2 only: the relaxed point rho x_bar + (1 - rho) x that the Halpern
+    // average uses (x_hat then holds 2 x_bar - x, the vector the y-step gathers); nullptr
+    // when rho = 2, where the two coincide
+    V *xrel = nullptr;
     V *xbar = nullptr, *zint = nullptr, *dx = nullptr;
     V *y = nullptr, *y0 = nullptr, *bd = nullptr, *sr = nullptr;
     V *ybar = nullptr, *dy = nullptr;
@@ -80,6 +84,7 @@ struct IterScalars {
     double hx0, hx1;    // x^{r,t} = hx0 * x0 + hx1 * x_hat     (Halpern weights at t)
     double hy0, hy1;    // y^{r,t+1} = hy0 * y0 + hy1 * y_hat   (Halpern weights at t)
     long long m1;       // first inequality row (single LP)
+    double rho = 2.0;   // relaxation: w_hat = rho w_bar + (1 - rho) w (2: Peaceman-Rachford)
 };
 
 // Per-instance scalars of a batched solve, read by the passes on the device (one set per
@@ -95,6 +100,7 @@ struct BatchArgs {
     const double *inv_norm = nullptr;  // power method normalisation per instance
     int iter_off = 0;
     int halpern = 1;
+    double rho = 2.0;
 };
 
 // Check-pass multipliers (always FP64).

@@ -79,7 +79,7 @@ template <> struct AccT<float, float> { using type = float; };
 // arrays of a batched solve.  Halpern weights of Algorithm 2 at inner counter t:
 // x^{r,t} = x0/(t+1) + t/(t+1) x_hat, y^{r,t+1} = y0/(t+2) + (t+1)/(t+2) y_hat.
 struct PassCtx {
-    double sigma, lam_sigma, hx0, hx1, hy0, hy1, inv_norm;
+    double sigma, lam_sigma, hx0, hx1, hy0, hy1, inv_norm, rho;
     long long m1_end;
     int active;
 };
@@ -92,6 +92,7 @@ __device__ __forceinline__ PassCtx ctx_single(const IterScalars &s, const double
     c.inv_norm = inv_norm ? *inv_norm : 1.0;
     c.m1_end = s.m1;
     c.active = 1;
+    c.rho = s.rho;
     return c;
 }
 
@@ -112,6 +113,7 @@ __device__ __forceinline__ PassCtx ctx_batch(const BatchArgs &b, int inst) {
     }
     c.m1_end = b.m1_end[inst];
     c.inv_norm = b.inv_norm ? b.inv_norm[inst] : 1.0;
+    c.rho = b.rho;
     return c;
 }
 
@@ -365,7 +367,9 @@ __global__ __launch_bounds__(kWG) void k_seg_reduce(const double *__restrict__ p
 //   x      = hx0 x0 + hx1 x_hat                 (x^{r,t}, rebuilt from the Halpern anchor)
 //   v      = x + sigma * s_j (g - c)             (s_j = dc_j^2 when the scaling is folded)
 //   x_bar  = Pi_C(v);   x_hat <- 2 x_bar - x     (gathered by the y-step)
-//   keep:  x_bar, z_int = (x_bar - v)/sigma (eq. update-z), dx = x - x_hat
+//   relaxation rho != 2: x_rel <- rho x_bar + (1 - rho) x is the Halpern point, and the next
+//   x is rebuilt from x_rel (x_rel = x_hat when rho = 2)
+//   keep:  x_bar, z_int = (x_bar - v)/sigma (eq. update-z), dx = x - (relaxed point)
 template <class M, class V, bool FOLD, bool KEEP, bool B> struct ColOp {
     using Sum = typename AccT<M, V>::type;
     using Raw = RawT<M>;
@@ -378,6 +382,7 @@ template <class M, class V, bool FOLD, bool KEEP, bool B> struct ColOp {
     const M *__restrict__ va;
     const V *__restrict__ yg;
     V *__restrict__ xhat;
+    V *__restrict__ xrel;  // nullptr when rho = 2
     const V *__restrict__ x0;
     const V *__restrict__ cd;
     const V *__restrict__ ld;
@@ -394,8 +399,8 @@ template <class M, class V, bool FOLD, bool KEEP, bool B> struct ColOp {
     __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
     __device__ __forceinline__ Sum prod(const Raw &r) const { return (Sum)r.a * (Sum)yg[r.j]; }
     __device__ __forceinline__ Pre load(int j) const {
-        return Pre{ep_load(xhat + j), ep_load(x0 + j), ep_load(cd + j), ep_load(ld + j),
-                   ep_load(ud + j), FOLD ? ep_load(sc + j) : (V)1};
+        return Pre{ep_load((xrel ? xrel : xhat) + j), ep_load(x0 + j), ep_load(cd + j),
+                   ep_load(ld + j), ep_load(ud + j), FOLD ? ep_load(sc + j) : (V)1};
     }
     __device__ __forceinline__ void apply(int j, Sum g, const Pre &p, const PassCtx &c,
                                           double *) const {
@@ -407,10 +412,15 @@ template <class M, class V, bool FOLD, bool KEEP, bool B> struct ColOp {
         const V xb = clampv(v, p.ld, p.ud);
         const V xr = (V)2 * xb - x;
         ep_store(xhat + j, xr);
+        V xh = xr;
+        if (xrel) {  // uniform
+            xh = (V)c.rho * xb + ((V)1 - (V)c.rho) * x;
+            xrel[j] = xh;
+        }
         if (KEEP) {
             xbar[j] = xb;
             zint[j] = (xb - v) / sigma;
-            dx[j] = x - xr;
+            dx[j] = x - xh;
         }
     }
 };
@@ -452,7 +462,8 @@ template <class M, class V, bool FOLD, bool KEEP, bool B> struct RowOp {
         if (FOLD) r = p.sr * r;
         V yb = p.y + r / (V)c.lam_sigma;
         if (i >= c.m1_end) yb = vmax(yb, (V)0);
-        const V yr = (V)2 * yb - p.y;
+        // relaxed point rho y_bar + (1 - rho) y (2 y_bar - y for rho = 2)
+        const V yr = c.rho == 2.0 ? (V)2 * yb - p.y : (V)c.rho * yb + ((V)1 - (V)c.rho) * p.y;
         y[i] = (V)c.hy0 * p.y0 + (V)c.hy1 * yr;
         if (KEEP) {
             ybar[i] = yb;
@@ -781,6 +792,7 @@ __global__ __launch_bounds__(kWG) void k_restart_batched(VecSet<V> v, const int 
         const V xb = v.xbar[j];
         v.x0[j] = xb;
         v.xhat[j] = xb;
+        if (v.xrel) v.xrel[j] = xb;
     }
     for (int i = row_off[b] + threadIdx.x; i < row_off[b + 1]; i += kWG) {
         const V yb = v.ybar[i];
@@ -824,8 +836,8 @@ hipError_t col_pass(const DevMat &T, const VecSet<V> &v, const IterScalars &s, h
     op.ci = T.ci;
     op.va = reinterpret_cast<const M *>(T.va);
     op.yg = v.y;
-    op.xhat = v.xhat; op.x0 = v.x0; op.cd = v.cd; op.ld = v.ld; op.ud = v.ud; op.sc = v.sc;
-    op.xbar = v.xbar; op.zint = v.zint; op.dx = v.dx;
+    op.xhat = v.xhat; op.xrel = v.xrel; op.x0 = v.x0; op.cd = v.cd; op.ld = v.ld; op.ud = v.ud;
+    op.sc = v.sc; op.xbar = v.xbar; op.zint = v.zint; op.dx = v.dx;
     set_scalars(op, s, ba);
     return run_pass(T, op, nullptr, st, ev);
 }

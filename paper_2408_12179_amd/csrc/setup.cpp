@@ -94,7 +94,7 @@ int validate_options(const hprlp_options &o, std::string &err) {
               o.tile_rows <= kMaxTileRows &&
               o.short_max >= 1 && o.short_max <= o.tile_nnz &&
               o.split_len >= o.short_max && o.chunk_nnz >= 256 && o.stall_ratio > 0 &&
-              o.stall_ratio <= 1;
+              o.stall_ratio <= 1 && o.rho > 0 && o.rho <= 2;
     if (!ok) err = "invalid option value";
     return ok ? HPRLP_OK : HPRLP_EINVAL;
 }
@@ -106,6 +106,7 @@ void resolve_options(hprlp_options &o) {
     if (o.split_len <= 0) o.split_len = 8192;
     if (o.chunk_nnz <= 0) o.chunk_nnz = 4096;
     if (o.stall_ratio == 0) o.stall_ratio = 0.5;
+    if (o.rho == 0) o.rho = 2.0;
 }
 
 // Transpose of a CSR matrix by counting sort over the column index.  pos[q] is the position

@@ -235,3 +235,10 @@ def test_workspace_covers_autotuner_candidates(lib):
 def test_step_rejects_null_handle(lib):
     assert lib.hprlp_step(None, 10) == hprlp.EINVAL
     assert lib.hprlp_last_error(None)
+
+
+def test_rho_out_of_range_is_rejected(lib):
+    lp = lpgen.make("tiny")
+    for rho in (-1.0, 2.5):
+        rc, msg = _create(lib, lp, rho=rho)
+        assert rc == hprlp.EINVAL, (rho, rc, msg)
