@@ -115,6 +115,10 @@ typedef struct {
     double rho;              /* relaxation of Algorithm 2: w_hat = rho w_bar + (1-rho) w,   */
                              /* in (0, 2]; 2 (default) = Peaceman-Rachford (HPR), 1 =        */
                              /* Douglas-Rachford (the paper's ablation, Section 4.2)         */
+    int setup_on_host;       /* 0 (default): create renumbers, transposes and scales the    */
+                             /* problem on the GPU, in scratch inside the workspace (which  */
+                             /* hprlp_workspace_bytes then includes); 1: on the host, with  */
+                             /* a smaller workspace.  Both give bit-identical arrays        */
 } hprlp_options;
 
 typedef struct {
@@ -139,6 +143,9 @@ typedef struct {
                              /* instances that had stopped                                  */
     double t_setup_ms;       /* hprlp_create: validation, preconditioning, transpose,       */
                              /* schedules (and autotuning), upload                          */
+    double t_prep_ms;        /* the part of t_setup_ms from the renumbering to the data     */
+                             /* vectors (host or device preprocessing, uploads included)    */
+    double t_tune_ms;        /* the part of t_setup_ms spent autotuning the schedules       */
 } hprlp_stats_t;
 
 /* Iterates that hprlp_get_iterate can return (original space unless noted). */

@@ -125,6 +125,8 @@ struct hprlp_handle {
     bool compacted = false;
     long long n_compactions = 0;
     double t_setup_ms = 0.0;                  // duration of create
+    double t_prep_ms = 0.0, t_tune_ms = 0.0;  // create: preprocessing, schedule autotuning
+    PrepScratch prep;                         // device preprocessing scratch (create only)
     // solve state (single LP)
     int prec = 0;
     long long t = 0, k = 0, r = 0;
@@ -160,6 +162,7 @@ struct Plan {
     int power_cap;
     int n_inst;
     bool batched;
+    bool prep = false;   // scratch of the device preprocessing
 };
 
 void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
@@ -244,7 +247,30 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         b.active = cv.arr<int>(1);
         b.inv_norm = inv_norm;
     }
+    PrepScratch ps;
+    if (p.prep) {  // last: nothing of the solve lives after it
+        for (auto &b2 : ps.u) b2 = cv.arr<uint32_t>(nnz);
+        ps.vr = cv.arr<double>(nnz);
+        if (p.mixed) {
+            ps.va64 = cv.arr<double>(nnz);
+            ps.vt64 = cv.arr<double>(nnz);
+        }
+        ps.cnt = cv.arr<uint32_t>(n + 1);
+        for (int q = 0; q < 2; ++q) {
+            ps.dk[q] = cv.arr<uint32_t>(n);
+            ps.dv[q] = cv.arr<uint32_t>(n);
+        }
+        ps.inv = cv.arr<uint32_t>(n);
+        ps.rf = cv.arr<double>(m); ps.cf = cv.arr<double>(n);
+        ps.dr = cv.arr<double>(m); ps.dc = cv.arr<double>(n);
+        ps.braw = cv.arr<double>(m); ps.craw = cv.arr<double>(n);
+        ps.lraw = cv.arr<double>(n); ps.uraw = cv.arr<double>(n);
+        ps.cst = cv.arr<double>(8 * ni);
+        ps.hist = cv.arr<uint32_t>(prep_hist_words(p.nnz, p.n));
+        ps.part = cv.arr<uint32_t>(prep_part_words(p.nnz, p.n));
+    }
     if (h) {
+        h->prep = ps;
         h->A.rp = A.rp; h->A.ci = A.ci; h->A.va = A.va; h->A.items = A.items;
         h->A.splits = A.splits; h->A.split_part = A.split_part;
         h->T.rp = T.rp; h->T.ci = T.ci; h->T.va = T.va; h->T.items = T.items;
@@ -290,6 +316,7 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n
     p.power_cap = power_cap(o);
     p.n_inst = n_inst;
     p.batched = batched;
+    p.prep = !o.setup_on_host;
     return p;
 }
 
@@ -347,16 +374,11 @@ struct Layout {
     bool batched;
 };
 
-// Device part of create: upload matrices (int32 row pointers), schedules, data vectors in
-// the pass coordinates, check multipliers, unscaling vectors and per-instance constants.
-int create_device(hprlp_handle *h, const Layout &L, const int64_t *rowptr,
-                  const int32_t *colidx, const double *val, const double *b, const double *c,
-                  const double *l, const double *u, const std::vector<int64_t> &rpt,
-                  const std::vector<int32_t> &cit, const std::vector<int32_t> &pos,
-                  const Scaling &sc, const std::vector<int32_t> &order,
-                  const std::vector<int32_t> &inst_row, const std::vector<int32_t> &inst_col,
-                  const std::vector<std::array<double, 8>> &cst) {
-    const hprlp_options &o = h->opt;
+// Host preprocessing path of create: upload A, A^T (int32 row pointers) and the renumbering.
+int upload_matrix_host(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
+                       const double *val, const std::vector<int64_t> &rpt,
+                       const std::vector<int32_t> &cit, const std::vector<int32_t> &pos,
+                       const Scaling &sc, const std::vector<int32_t> &order) {
     const int64_t m = h->m, n = h->n, nnz = h->nnz;
     int rc;
     {
@@ -381,13 +403,18 @@ int create_device(hprlp_handle *h, const Layout &L, const int64_t *rowptr,
         for (int64_t q = 0; q < nnz; ++q) vt[q] = sc.val[pos[q]];
         if ((rc = upload(h, (double *)h->T.va, vt.data(), (size_t)nnz))) return rc;
     }
-    for (DevMat *M : {&h->A, &h->T}) {
-        if ((rc = upload(h, M->items, M->host.items.data(), M->host.items.size()))) return rc;
-        if ((rc = upload(h, M->splits, M->host.splits.data(), M->host.splits.size())))
-            return rc;
-    }
-    // data vectors in the pass coordinates, check multipliers and unscaling; every row and
-    // column uses the normalisation factors beta_b, beta_c of its own instance
+    return HPRLP_OK;
+}
+
+// Host preprocessing path of create: data vectors in the pass coordinates, check
+// multipliers and unscaling; every row and column uses the normalisation factors beta_b,
+// beta_c of its own instance.  c, l, u in the internal column order.
+int upload_vectors_host(hprlp_handle *h, const double *b, const double *c, const double *l,
+                        const double *u, const Scaling &sc, const std::vector<int32_t> &inst_row,
+                        const std::vector<int32_t> &inst_col,
+                        const std::vector<std::array<double, 8>> &cst) {
+    const int64_t m = h->m, n = h->n;
+    int rc;
     std::vector<double> cd(n), ld(n), ud(n), bd(m), co(n), csv(n), xs(n), ro(m), rs(m), ys(m),
         ux(n), uy(m), sc2, sr2;
     for (int64_t j = 0; j < n; ++j) {
@@ -453,6 +480,20 @@ int create_device(hprlp_handle *h, const Layout &L, const int64_t *rowptr,
             (rc = upf(h->v32.bd, bd)) || (rc = upf(h->v32.sc, sc2)) || (rc = upf(h->v32.sr, sr2)))
             return rc;
     }
+    return HPRLP_OK;
+}
+
+// Both paths of create: schedules, instance structure and constants, single-LP flags, and
+// the pinned staging buffer.
+int upload_common(hprlp_handle *h, const Layout &L,
+                  const std::vector<std::array<double, 8>> &cst) {
+    const hprlp_options &o = h->opt;
+    int rc;
+    for (DevMat *M : {&h->A, &h->T}) {
+        if ((rc = upload(h, M->items, M->host.items.data(), M->host.items.size()))) return rc;
+        if ((rc = upload(h, M->splits, M->host.splits.data(), M->host.splits.size())))
+            return rc;
+    }
     if (!L.batched) {
         const int m1e = (int)L.m1[0], one = 1;
         if ((rc = upload(h, h->bd.m1_end, &m1e, 1)) || (rc = upload(h, h->bd.active, &one, 1)))
@@ -489,6 +530,98 @@ int create_device(hprlp_handle *h, const Layout &L, const int64_t *rowptr,
     }
     h->pinned_len = std::max<size_t>(4 * kNQ + 64, (size_t)power_cap(o) * L.n_inst);
     HIPCHK(h, hipHostMalloc((void **)&h->pinned, h->pinned_len * sizeof(double), 0));
+    return HPRLP_OK;
+}
+
+// Per instance: beta_b = ||D_r b|| + 1, beta_c = ||D_c c|| + 1 (Section 4.1) and the norms
+// the termination test divides by.  dc and c in the internal column order.
+std::vector<std::array<double, 8>> instance_constants(const Layout &L, const hprlp_options &o,
+                                                      const double *dr, const double *dc,
+                                                      const double *b, const double *c) {
+    std::vector<std::array<double, 8>> cst(L.n_inst);
+    for (int bi = 0; bi < L.n_inst; ++bi) {
+        const int64_t r0 = L.row_off[bi], r1 = L.row_off[bi + 1];
+        const int64_t c0 = L.col_off[bi], c1 = L.col_off[bi + 1];
+        double sb = 0, scc = 0, sbo = 0, sco = 0;
+        for (int64_t i = r0; i < r1; ++i) {
+            const double v = dr[i] * b[i];
+            sb += v * v;
+            sbo += b[i] * b[i];
+        }
+        for (int64_t j = c0; j < c1; ++j) {
+            const double v = dc[j] * c[j];
+            scc += v * v;
+            sco += c[j] * c[j];
+        }
+        const double bb = o.normalize_bc ? std::sqrt(sb) + 1.0 : 1.0;
+        const double bc = o.normalize_bc ? std::sqrt(scc) + 1.0 : 1.0;
+        double sbn = 0, scn = 0;  // ||D_r b / beta_b||, ||D_c c / beta_c||
+        for (int64_t i = r0; i < r1; ++i) {
+            const double v = dr[i] * b[i] / bb;
+            sbn += v * v;
+        }
+        for (int64_t j = c0; j < c1; ++j) {
+            const double v = dc[j] * c[j] / bc;
+            scn += v * v;
+        }
+        cst[bi] = {bb, bc, std::sqrt(sbo), std::sqrt(sco), std::sqrt(sbn), std::sqrt(scn), 0.0, 0.0};
+    }
+    return cst;
+}
+
+PrepArgs prep_args(const hprlp_handle *h) {
+    PrepArgs a;
+    a.m = h->m;
+    a.n = h->n;
+    a.nnz = h->nnz;
+    a.reorder = h->opt.reorder != 0;
+    a.mixed = h->mixed;
+    a.f32phase = h->f32phase;
+    a.ruiz_iters = h->opt.ruiz_iters;
+    a.pock_chambolle = h->opt.pock_chambolle != 0;
+    a.A = const_cast<DevMat *>(&h->A);
+    a.T = const_cast<DevMat *>(&h->T);
+    a.cperm = h->cperm;
+    a.s = h->prep;
+    return a;
+}
+
+// Device preprocessing path of create, first part: upload the problem as given, renumber,
+// transpose and scale on the GPU, and bring back what the host needs (A^T's row pointers,
+// D_r, D_c and the renumbering).  Returns c in the internal column order in c_int.
+int prep_on_device(hprlp_handle *h, const int64_t *rowptr, const int32_t *colidx,
+                   const double *val, const double *b, const double *c, const double *l,
+                   const double *u, std::vector<int64_t> &rpt, std::vector<double> &dr,
+                   std::vector<double> &dc, std::vector<double> &c_int) {
+    const int64_t m = h->m, n = h->n, nnz = h->nnz;
+    const PrepScratch &s = h->prep;
+    int rc;
+    {
+        std::vector<int> rp32((size_t)m + 1);
+        for (int64_t i = 0; i <= m; ++i) rp32[i] = (int)rowptr[i];
+        if ((rc = upload(h, h->A.rp, rp32.data(), (size_t)m + 1))) return rc;
+    }
+    if ((rc = upload(h, h->A.ci, colidx, (size_t)nnz)) || (rc = upload(h, s.vr, val, (size_t)nnz)) ||
+        (rc = upload(h, s.braw, b, (size_t)m)) || (rc = upload(h, s.craw, c, (size_t)n)) ||
+        (rc = upload(h, s.lraw, l, (size_t)n)) || (rc = upload(h, s.uraw, u, (size_t)n)))
+        return rc;
+    PrepArgs a = prep_args(h);
+    HIPCHK(h, prep_matrix(a, h->st));
+    std::vector<int> t32((size_t)n + 1), order((size_t)n);
+    dr.resize((size_t)m);
+    dc.resize((size_t)n);
+    if ((rc = download(h, t32.data(), h->T.rp, (size_t)n + 1)) ||
+        (rc = download(h, order.data(), h->cperm, (size_t)n)) ||
+        (rc = download(h, dr.data(), s.dr, (size_t)m)) ||
+        (rc = download(h, dc.data(), s.dc, (size_t)n)))
+        return rc;
+    rpt.resize((size_t)n + 1);
+    for (int64_t j = 0; j <= n; ++j) rpt[j] = t32[j];
+    c_int.resize((size_t)n);
+    for (int64_t j = 0; j < n; ++j) c_int[j] = c[order[j]];
+    h->dr = dr;
+    h->dc.assign((size_t)n, 1.0);
+    for (int64_t j = 0; j < n; ++j) h->dc[order[j]] = dc[j];  // caller's column order
     return HPRLP_OK;
 }
 
@@ -574,151 +707,163 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     h->st = h->user_st;
     if (lambda_inst) h->lam_given.assign(lambda_inst, lambda_inst + L.n_inst);
 
-    // ---- host preprocessing
-    // Column renumbering by decreasing nonzero count (single LP): the most gathered entries
-    // of x_hat then share cache lines.  It permutes the variables only; every output is
-    // scattered back to the caller's order.
-    std::vector<int32_t> order((size_t)n), colr;
-    std::vector<double> valr, cr, lr, ur;
-    for (int64_t j = 0; j < n; ++j) order[j] = (int32_t)j;
-    if (o.reorder) {
-        std::vector<int64_t> deg((size_t)n, 0);
-        for (int64_t p = 0; p < nnz; ++p) deg[colidx[p]]++;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b2) { return deg[a] > deg[b2]; });
-        std::vector<int32_t> inv((size_t)n);
-        for (int64_t j = 0; j < n; ++j) inv[order[j]] = (int32_t)j;
-        colr.resize((size_t)nnz);
-        valr.resize((size_t)nnz);
-        std::vector<std::pair<int32_t, double>> rowbuf;
-        for (int64_t i = 0; i < m; ++i) {
-            rowbuf.clear();
-            for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
-                rowbuf.push_back({inv[colidx[p]], val[p]});
-            std::sort(rowbuf.begin(), rowbuf.end(),
-                      [](const std::pair<int32_t, double> &a,
-                         const std::pair<int32_t, double> &b2) { return a.first < b2.first; });
-            for (size_t q = 0; q < rowbuf.size(); ++q) {
-                colr[rowptr[i] + q] = rowbuf[q].first;
-                valr[rowptr[i] + q] = rowbuf[q].second;
-            }
-        }
-        cr.resize((size_t)n); lr.resize((size_t)n); ur.resize((size_t)n);
-        for (int64_t j = 0; j < n; ++j) {
-            cr[j] = c[order[j]];
-            lr[j] = l[order[j]];
-            ur[j] = u[order[j]];
-        }
-        colidx = colr.data();
-        val = valr.data();
-        c = cr.data();
-        l = lr.data();
-        u = ur.data();
-    }
-    std::vector<int64_t> rpt;
-    std::vector<int32_t> cit, pos;
-    transpose(m, n, rowptr, colidx, rpt, cit, pos);
-    Scaling sc;
-    precondition(m, n, rowptr, colidx, rpt, pos, val, o, sc);
-    h->dr = sc.dr;
-    h->dc.assign((size_t)n, 1.0);
-    for (int64_t j = 0; j < n; ++j) h->dc[order[j]] = sc.dc[j];  // caller's column order
-
-    // instance of every row and column; per instance: beta_b = ||D_r b|| + 1,
-    // beta_c = ||D_c c|| + 1 (Section 4.1) and the norms the termination test divides by
+    // instance of every row and column
     std::vector<int32_t> inst_row((size_t)m), inst_col((size_t)n);
     for (int bi = 0; bi < L.n_inst; ++bi) {
         for (int64_t i = L.row_off[bi]; i < L.row_off[bi + 1]; ++i) inst_row[i] = bi;
         for (int64_t j = L.col_off[bi]; j < L.col_off[bi + 1]; ++j) inst_col[j] = bi;
     }
-    std::vector<std::array<double, 8>> cst(L.n_inst);
-    for (int bi = 0; bi < L.n_inst; ++bi) {
-        const int64_t r0 = L.row_off[bi], r1 = L.row_off[bi + 1];
-        const int64_t c0 = L.col_off[bi], c1 = L.col_off[bi + 1];
-        double sb = 0, scc = 0, sbo = 0, sco = 0;
-        for (int64_t i = r0; i < r1; ++i) {
-            const double v = sc.dr[i] * b[i];
-            sb += v * v;
-            sbo += b[i] * b[i];
-        }
-        for (int64_t j = c0; j < c1; ++j) {
-            const double v = sc.dc[j] * c[j];
-            scc += v * v;
-            sco += c[j] * c[j];
-        }
-        const double bb = o.normalize_bc ? std::sqrt(sb) + 1.0 : 1.0;
-        const double bc = o.normalize_bc ? std::sqrt(scc) + 1.0 : 1.0;
-        double sbn = 0, scn = 0;  // ||D_r b / beta_b||, ||D_c c / beta_c||
-        for (int64_t i = r0; i < r1; ++i) {
-            const double v = sc.dr[i] * b[i] / bb;
-            sbn += v * v;
-        }
-        for (int64_t j = c0; j < c1; ++j) {
-            const double v = sc.dc[j] * c[j] / bc;
-            scn += v * v;
-        }
-        cst[bi] = {bb, bc, std::sqrt(sbo), std::sqrt(sco), std::sqrt(sbn), std::sqrt(scn), 0.0, 0.0};
-    }
-    h->beta_b = cst[0][0];
-    h->beta_c = cst[0][1];
-    h->bnorm = cst[0][2];
-    h->cnorm = cst[0][3];
-    h->bsnorm = cst[0][4];
-    h->csnorm = cst[0][5];
-
     const ScheduleParams spar{o.tile_nnz, o.tile_rows, o.short_max, o.split_len, o.chunk_nnz};
     h->spA = h->spT = spar;
-    build_schedule(m, rowptr, spar, L.batched ? inst_row.data() : nullptr, h->A.host);
-    build_schedule(n, rpt.data(), spar, L.batched ? inst_col.data() : nullptr, h->T.host);
-
-    // carved sizes: the schedules just built, or the bound over every autotuner candidate
+    const int32_t *irow = L.batched ? inst_row.data() : nullptr;
+    const int32_t *icol = L.batched ? inst_col.data() : nullptr;
+    auto build_schedules = [&](const int64_t *rpT) {
+        build_schedule(m, rowptr, spar, irow, h->A.host);
+        build_schedule(n, rpT, spar, icol, h->T.host);
+        for (DevMat *M : {&h->A, &h->T}) {
+            M->n_items = (int)M->host.items.size();
+            M->n_split = (int)M->host.splits.size();
+            M->tile_nnz = M->host.tile_nnz;
+            M->tile_rows = M->host.tile_rows;
+        }
+    };
+    // carve the workspace (sizes: the schedules already built, or the bound over every
+    // autotuner candidate) and set up the stream; false + h deleted on failure
+    auto carve_all = [&](Plan need) -> int {
+        if (plan_bytes(need) > ws_bytes) {
+            delete h;
+            return fail(nullptr, HPRLP_EINVAL, "workspace too small: need " +
+                                                   std::to_string(plan_bytes(need)) + " bytes");
+        }
+        Carver cv{static_cast<char *>(d_workspace), ws_bytes, 0, false};
+        carve(cv, need, h);
+        h->A.rows = (int)m;
+        h->T.rows = (int)n;
+        h->capA[0] = need.itemsA; h->capA[1] = need.splitA; h->capA[2] = need.slotsA;
+        h->capT[0] = need.itemsT; h->capT[1] = need.splitT; h->capT[2] = need.slotsT;
+        h->sched_nnz = nnz;
+        if (L.batched) {
+            // batched work is ordered on a stream of the library's own (stream capture needs
+            // a stream other than the legacy default one); each entry point first waits for
+            // the caller's stream
+            if (h->user_st && hipStreamSynchronize(h->user_st) != hipSuccess) {
+                delete h;
+                return fail(nullptr, HPRLP_EHIP, "caller stream synchronisation failed");
+            }
+            if (hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) != hipSuccess) {
+                delete h;
+                return fail(nullptr, HPRLP_EHIP, "hipStreamCreateWithFlags failed");
+            }
+            h->own_stream = true;
+        }
+        return HPRLP_OK;
+    };
     Plan need = bound_plan(m, n, nnz, o, L.n_inst, L.batched);
-    if (!o.autotune) {
-        need.itemsA = (int)h->A.host.items.size();
-        need.itemsT = (int)h->T.host.items.size();
-        need.splitA = (int)h->A.host.splits.size();
-        need.splitT = (int)h->T.host.splits.size();
-        need.slotsA = h->A.host.n_chunk_slots;
-        need.slotsT = h->T.host.n_chunk_slots;
-    }
-    if (plan_bytes(need) > ws_bytes) {
-        delete h;
-        return fail(nullptr, HPRLP_EINVAL, "workspace too small: need " +
-                                               std::to_string(plan_bytes(need)) + " bytes");
-    }
-    Carver cv{static_cast<char *>(d_workspace), ws_bytes, 0, false};
-    carve(cv, need, h);
-    for (DevMat *M : {&h->A, &h->T}) {
-        M->n_items = (int)M->host.items.size();
-        M->n_split = (int)M->host.splits.size();
-        M->tile_nnz = M->host.tile_nnz;
-        M->tile_rows = M->host.tile_rows;
-    }
-    h->A.rows = (int)m;
-    h->T.rows = (int)n;
-    h->capA[0] = need.itemsA; h->capA[1] = need.splitA; h->capA[2] = need.slotsA;
-    h->capT[0] = need.itemsT; h->capT[1] = need.splitT; h->capT[2] = need.slotsT;
-    h->sched_nnz = nnz;
+    std::vector<int64_t> rpt;
+    std::vector<std::array<double, 8>> cst;
+    const double t_prep = now_ms();
 
-    if (L.batched) {
-        // batched work is ordered on a stream of the library's own (stream capture needs a
-        // stream other than the legacy default one); each entry point first waits for the
-        // caller's stream
-        if (h->user_st && hipStreamSynchronize(h->user_st) != hipSuccess) {
-            delete h;
-            return fail(nullptr, HPRLP_EHIP, "caller stream synchronisation failed");
+    if (o.setup_on_host) {
+        // ---- host preprocessing
+        // Column renumbering by decreasing nonzero count (single LP): the most gathered
+        // entries of x_hat then share cache lines.  It permutes the variables only; every
+        // output is scattered back to the caller's order.
+        std::vector<int32_t> order((size_t)n), colr;
+        std::vector<double> valr, cr, lr, ur;
+        for (int64_t j = 0; j < n; ++j) order[j] = (int32_t)j;
+        if (o.reorder) {
+            std::vector<int64_t> deg((size_t)n, 0);
+            for (int64_t p = 0; p < nnz; ++p) deg[colidx[p]]++;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t a, int32_t b2) { return deg[a] > deg[b2]; });
+            std::vector<int32_t> inv((size_t)n);
+            for (int64_t j = 0; j < n; ++j) inv[order[j]] = (int32_t)j;
+            colr.resize((size_t)nnz);
+            valr.resize((size_t)nnz);
+            std::vector<std::pair<int32_t, double>> rowbuf;
+            for (int64_t i = 0; i < m; ++i) {
+                rowbuf.clear();
+                for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+                    rowbuf.push_back({inv[colidx[p]], val[p]});
+                std::sort(rowbuf.begin(), rowbuf.end(),
+                          [](const std::pair<int32_t, double> &a,
+                             const std::pair<int32_t, double> &b2) { return a.first < b2.first; });
+                for (size_t q = 0; q < rowbuf.size(); ++q) {
+                    colr[rowptr[i] + q] = rowbuf[q].first;
+                    valr[rowptr[i] + q] = rowbuf[q].second;
+                }
+            }
+            cr.resize((size_t)n); lr.resize((size_t)n); ur.resize((size_t)n);
+            for (int64_t j = 0; j < n; ++j) {
+                cr[j] = c[order[j]];
+                lr[j] = l[order[j]];
+                ur[j] = u[order[j]];
+            }
+            colidx = colr.data();
+            val = valr.data();
+            c = cr.data();
+            l = lr.data();
+            u = ur.data();
         }
-        if (hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) != hipSuccess) {
-            delete h;
-            return fail(nullptr, HPRLP_EHIP, "hipStreamCreateWithFlags failed");
+        std::vector<int32_t> cit, pos;
+        transpose(m, n, rowptr, colidx, rpt, cit, pos);
+        Scaling sc;
+        precondition(m, n, rowptr, colidx, rpt, pos, val, o, sc);
+        h->dr = sc.dr;
+        h->dc.assign((size_t)n, 1.0);
+        for (int64_t j = 0; j < n; ++j) h->dc[order[j]] = sc.dc[j];  // caller's column order
+        cst = instance_constants(L, o, sc.dr.data(), sc.dc.data(), b, c);
+        build_schedules(rpt.data());
+        if (!o.autotune) {
+            need.itemsA = (int)h->A.host.items.size();
+            need.itemsT = (int)h->T.host.items.size();
+            need.splitA = (int)h->A.host.splits.size();
+            need.splitT = (int)h->T.host.splits.size();
+            need.slotsA = h->A.host.n_chunk_slots;
+            need.slotsT = h->T.host.n_chunk_slots;
         }
-        h->own_stream = true;
+        if ((rc = carve_all(need))) return rc;
+        rc = upload_matrix_host(h, rowptr, colidx, val, rpt, cit, pos, sc, order);
+        if (!rc) rc = upload_vectors_host(h, b, c, l, u, sc, inst_row, inst_col, cst);
+        if (!rc) rc = upload_common(h, L, cst);
+    } else {
+        // ---- device preprocessing: the same arrays, computed in the workspace
+        if ((rc = carve_all(need))) return rc;
+        std::vector<double> dr, dc, c_int;
+        rc = prep_on_device(h, rowptr, colidx, val, b, c, l, u, rpt, dr, dc, c_int);
+        if (!rc) {
+            cst = instance_constants(L, o, dr.data(), dc.data(), b, c_int.data());
+            build_schedules(rpt.data());
+            rc = upload_common(h, L, cst);
+        }
+        if (!rc && !L.batched) {
+            std::vector<double> c0(cst[0].begin(), cst[0].end());
+            rc = upload(h, h->prep.cst, c0.data(), c0.size());
+        }
+        if (!rc) {
+            const PrepArgs a = prep_args(h);
+            const double *dcst = L.batched ? h->bd.cst : h->prep.cst;
+            hipError_t e = prep_vectors(a, L.batched ? h->bd.row_off : nullptr,
+                                        L.batched ? h->bd.col_off : nullptr, L.n_inst, dcst,
+                                        h->v64, h->v32, h->chk, h->ux, h->uy, h->st);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+            if (e != hipSuccess)
+                rc = fail(h, HPRLP_EHIP, std::string("device preprocessing: ") + hipGetErrorString(e));
+        }
     }
-    rc = create_device(h, L, rowptr, colidx, val, b, c, l, u, rpt, cit, pos, sc, order,
-                       inst_row, inst_col, cst);
+    if (!rc) {  // single LP: the normalisation and the norms of the termination test
+        h->beta_b = cst[0][0];
+        h->beta_c = cst[0][1];
+        h->bnorm = cst[0][2];
+        h->cnorm = cst[0][3];
+        h->bsnorm = cst[0][4];
+        h->csnorm = cst[0][5];
+    }
+    h->t_prep_ms = now_ms() - t_prep;
+    const double t_tune = now_ms();
     if (!rc && o.autotune && nnz >= kTuneMinNnz)
-        rc = tune_schedules(h, rowptr, rpt.data(), L.batched ? inst_row.data() : nullptr,
-                            L.batched ? inst_col.data() : nullptr);
+        rc = tune_schedules(h, rowptr, rpt.data(), irow, icol);
+    h->t_tune_ms = now_ms() - t_tune;
     if (rc) {
         g_create_error = h->err;
         hprlp_destroy(h);
@@ -1515,6 +1660,8 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
     s.split_ms = split_ms;
     s.n_checks = (long long)h->trace.size();
     s.t_setup_ms = h->t_setup_ms;
+    s.t_prep_ms = h->t_prep_ms;
+    s.t_tune_ms = h->t_tune_ms;
     if (status) *status = st_out;
     return HPRLP_OK;
 }
@@ -1757,6 +1904,8 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
     s.n_checks = k / o.check_every;
     s.n_compactions = h->n_compactions;
     s.t_setup_ms = h->t_setup_ms;
+    s.t_prep_ms = h->t_prep_ms;
+    s.t_tune_ms = h->t_tune_ms;
     if (status) *status = worst;
     return HPRLP_OK;
 }

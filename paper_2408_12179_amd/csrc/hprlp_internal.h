@@ -172,6 +172,46 @@ hipError_t launch_restart_batched(bool f32, const void *vecset, const int *row_o
                                   const int *col_off, const int *restart_flag, int n_inst,
                                   hipStream_t st);
 hipError_t launch_advance(long long *kbase, int chunk, hipStream_t st);
+// ---------------------------------------------------------------- device preprocessing
+// (prep.hip) The column renumbering, transpose, scaling and data vectors of create, on the
+// GPU, with the same results as the host preprocessing.
+constexpr int kSortTile = 4096;  // radix sort: items per block
+
+// Scratch of the device preprocessing, carved after the solver's arrays in the workspace.
+struct PrepScratch {
+    uint32_t *u[6] = {};                       // [nnz] each: sort buffers and index maps
+    double *vr = nullptr;                      // [nnz] A's values as given (caller's order)
+    double *va64 = nullptr, *vt64 = nullptr;   // [nnz] FP32 storage of A: FP64 scaled copies
+    uint32_t *cnt = nullptr;                   // [n + 1] counts, then A^T's row pointers
+    uint32_t *dk[2] = {}, *dv[2] = {};         // [n] each: the column-order sort
+    uint32_t *inv = nullptr;                   // [n] caller's column -> internal column
+    double *rf = nullptr, *cf = nullptr;       // [m], [n] factors of one scaling pass
+    double *dr = nullptr, *dc = nullptr;       // [m], [n] products D_r, D_c
+    double *braw = nullptr, *craw = nullptr, *lraw = nullptr, *uraw = nullptr;  // as given
+    double *cst = nullptr;                     // [n_inst][8] per-instance constants
+    uint32_t *hist = nullptr, *part = nullptr; // radix sort digit counts, scan block sums
+};
+
+struct PrepArgs {
+    int64_t m = 0, n = 0, nnz = 0;
+    bool reorder = false, mixed = false, f32phase = false;
+    int ruiz_iters = 0;
+    bool pock_chambolle = false;
+    DevMat *A = nullptr, *T = nullptr;  // in: A.rp, A.ci (caller's columns); out: the rest
+    int *cperm = nullptr;               // out: internal column -> caller's column
+    PrepScratch s;                      // in: vr, braw, craw, lraw, uraw; out: dr, dc
+};
+
+size_t prep_hist_words(int64_t nnz, int64_t n);
+size_t prep_part_words(int64_t nnz, int64_t n);
+// Column order, A (re-sorted rows), A^T, the scaled values (or FP32 originals) and D_r, D_c.
+hipError_t prep_matrix(const PrepArgs &a, hipStream_t st);
+// Data vectors in the pass coordinates from D_r, D_c and the per-instance constants cst
+// (row_off / col_off: instance offsets on the device, nullptr for one LP).
+hipError_t prep_vectors(const PrepArgs &a, const int *row_off, const int *col_off, int n_inst,
+                        const double *cst, const VecSet<double> &d, const VecSet<float> &f,
+                        const CheckData &c, double *ux, double *uy, hipStream_t st);
+
 // vector utilities
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t st);
 hipError_t launch_fill_f(float *p, long long n, float v, hipStream_t st);

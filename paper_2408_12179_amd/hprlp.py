@@ -46,7 +46,7 @@ class Options(C.Structure):
                 ("tile_rows", C.c_int), ("short_max", C.c_int), ("split_len", C.c_int),
                 ("chunk_nnz", C.c_int), ("reorder", C.c_int), ("profile", C.c_int),
                 ("verbose", C.c_int), ("autotune", C.c_int), ("stall_ratio", C.c_double),
-                ("graph", C.c_int), ("rho", C.c_double)]
+                ("graph", C.c_int), ("rho", C.c_double), ("setup_on_host", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -60,7 +60,8 @@ class Stats(C.Structure):
                 ("row_pass_ms", C.c_double), ("col_pass_launches", C.c_longlong),
                 ("row_pass_launches", C.c_longlong), ("split_ms", C.c_double),
                 ("n_checks", C.c_longlong), ("n_compactions", C.c_longlong),
-                ("t_setup_ms", C.c_double)]
+                ("t_setup_ms", C.c_double), ("t_prep_ms", C.c_double),
+                ("t_tune_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

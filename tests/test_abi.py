@@ -242,3 +242,18 @@ def test_rho_out_of_range_is_rejected(lib):
     for rho in (-1.0, 2.5):
         rc, msg = _create(lib, lp, rho=rho)
         assert rc == hprlp.EINVAL, (rho, rc, msg)
+
+
+def test_device_setup_scratch_is_in_the_workspace(lib):
+    # the device preprocessing works inside the caller's workspace: at least 32 bytes per
+    # nonzero more than the host preprocessing needs (sort buffers and the values as given)
+    nnz = 10**6
+    dev = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options())
+    host = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options(setup_on_host=1))
+    assert dev - host >= 32 * nnz
+    mixed = hprlp.workspace_bytes(5000, 5000, 20000, nnz,
+                                  hprlp.default_options(precision=hprlp.MIXED))
+    mixed_host = hprlp.workspace_bytes(5000, 5000, 20000, nnz,
+                                       hprlp.default_options(precision=hprlp.MIXED,
+                                                             setup_on_host=1))
+    assert mixed - mixed_host >= 48 * nnz

@@ -72,3 +72,27 @@ def test_fullsize_batch256_sampled_instances():
         print("batch256 instance", i, inst.m, inst.n, f"{ex:.2e} {ey:.2e} {ez:.2e}")
         assert max(ex, ey, ez) <= 1e-10, (i, ex, ey, ez)
     s.close()
+
+
+@pytest.mark.parametrize("name", ["zipf1m", "transport10m", "batch256"])
+def test_fullsize_device_setup_matches_host(name):
+    """Device and host preprocessing at the full sizes: the same schedules and bit-identical
+    iterates after 30 iterations (every array the passes read enters them)."""
+    lp = lpgen.make(name)
+    batched = name == "batch256"
+    ni = len(lp.inst_m1) if batched else 1
+    opt = dict(max_iter=30, check_every=10, lambda_override=1.0) if not batched else \
+        dict(max_iter=30, check_every=10, lambdas=np.ones(ni))
+    if name == "transport10m":
+        opt["precision"] = hprlp.MIXED
+    res = []
+    for host in (1, 0):
+        s = hprlp.Solver(lp, batched=batched, setup_on_host=host, **opt)
+        sol = s.solve()
+        res.append((sol.x, sol.y, sol.z, s.schedule(0), s.schedule(1), sol.stats["t_prep_ms"]))
+        s.close()
+    (xh, yh, zh, ah, th, ph), (xd, yd, zd, ad, td, pd) = res
+    print(name, "preprocessing ms host / device", round(ph, 1), round(pd, 1))
+    assert ah == ad and th == td
+    for a, b in ((xh, xd), (yh, yd), (zh, zd)):
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
