@@ -15,6 +15,8 @@ U{5..40}; Zipf(1.1) column popularity; plain FP64).  --config selects the other 
   batch256      256 independent LPs (m_i ~ U{1k..50k}, n_i = 2 m_i) packed block-diagonally,
                 solved in one batched run (check_every = 100)
   transport10m  2000 x 5000 transportation LP (n = 10M), FP32 -> FP64
+  qap40         LP relaxation of a random QAP with N = 40 in the form of Section 4.4
+                (n = 2.56M, m = 1.41M equality rows, nnz = 7.8M), FP64
 --compare adds the plain-FP64 GPU solver on the same instances under the same time budget:
 the FP64 single-LP solve for the mixed-precision workloads, and for batch256 the single-LP
 FP64 solver run on the instances one after another.
@@ -152,7 +154,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default="zipf1m",
-                    choices=["tiny", "zipf1m", "zipf4m", "batch256", "transport10m"])
+                    choices=["tiny", "zipf1m", "zipf4m", "batch256", "transport10m", "qap40"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "fp64a32"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--time-limit", type=float, default=60.0, help="seconds per solve")

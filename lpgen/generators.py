@@ -291,6 +291,64 @@ def transport_lp(n_src: int, n_dst: int, seed: int, name="transport") -> LP:
                         supply_factor=k))
 
 
+def qap_lp(N: int, seed: int, name="qap") -> LP:
+    """LP relaxation of a quadratic assignment problem, in the form of the paper's large QAP
+    experiments (Section 4.4, Adams-Johnson linearisation), every index running over 1..N.
+
+    Columns: s_ijkl >= 0 at ((i N + j) N + k) N + l, then 0 <= x_kl <= 1 at N^4 + k N + l.
+    Equality rows, in this order:
+      (a) sum_i s_ijkl - x_kl = 0  for every (j, k, l), row (j N + k) N + l
+      (b) sum_j s_ijkl - x_kl = 0  for every (i, k, l), row N^3 + (i N + k) N + l
+      (c) s_ijkl - s_klij = 0      for every pair p = i N + j < q = k N + l (q-major within p)
+      (d) sum_j x_ij = 1 for every i, then (e) sum_i x_ij = 1 for every j.
+    Cost a_ik b_jl on s_ijkl, 0 on x.  The flow matrix a and the distance matrix b are
+    symmetric with zero diagonal and integer entries U{0..99}, like uniformly random QAPLIB
+    instances (QAPLIB itself is not available); all data are exact in FP32.  No certificate:
+    the optimal value is that of the relaxation."""
+    rng = np.random.default_rng(seed)
+
+    def sym():
+        t = np.triu(rng.integers(0, 100, size=(N, N)), 1)
+        return (t + t.T).astype(np.float64)
+
+    flow, dist = sym(), sym()
+    N2, N3, N4 = N * N, N ** 3, N ** 4
+    ar = np.arange(N, dtype=np.int64)
+    xcol = lambda k, l: N4 + k * N + l  # noqa: E731
+    # (a): row (j, k, l) holds s_{i j k l} for i = 0..N-1, then x_kl
+    j, k, l = np.meshgrid(ar, ar, ar, indexing="ij")
+    j, k, l = j.ravel(), k.ravel(), l.ravel()
+    s_a = ((ar[None, :] * N + j[:, None]) * N + k[:, None]) * N + l[:, None]
+    cols_a = np.concatenate([s_a, xcol(k, l)[:, None]], axis=1)
+    # (b): row (i, k, l) holds s_{i j k l} for j = 0..N-1, then x_kl
+    i = j  # same (first, k, l) enumeration
+    s_b = ((i[:, None] * N + ar[None, :]) * N + k[:, None]) * N + l[:, None]
+    cols_b = np.concatenate([s_b, xcol(k, l)[:, None]], axis=1)
+    vals_ab = np.concatenate([np.ones((N3, N)), -np.ones((N3, 1))], axis=1)
+    # (c): pairs p < q
+    p, q = np.triu_indices(N2, 1)
+    cols_c = np.stack([p * N2 + q, q * N2 + p], axis=1)
+    vals_c = np.tile(np.array([1.0, -1.0]), (len(p), 1))
+    # (d), (e)
+    cols_d = N4 + ar[:, None] * N + ar[None, :]
+    cols_e = N4 + ar[None, :] * N + ar[:, None]
+    colidx = np.concatenate([cols_a.ravel(), cols_b.ravel(), cols_c.ravel(), cols_d.ravel(),
+                             cols_e.ravel()]).astype(np.int32)
+    val = np.concatenate([vals_ab.ravel(), vals_ab.ravel(), vals_c.ravel(),
+                          np.ones(2 * N2)])
+    lens = np.concatenate([np.full(2 * N3, N + 1), np.full(len(p), 2), np.full(2 * N, N)])
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    m = len(lens)
+    b = np.concatenate([np.zeros(m - 2 * N), np.ones(2 * N)])
+    n = N4 + N2
+    cost = np.zeros(n)
+    cost[:N4] = (flow[:, None, :, None] * dist[None, :, None, :]).ravel()  # a_ik b_jl
+    lo = np.zeros(n)
+    up = np.concatenate([np.full(N4, np.inf), np.ones(N2)])
+    return LP(name, m, 0, n, rowptr, colidx, val, b, cost, lo, up, None,
+              meta=dict(family="qap", N=N, seed=seed, flow=flow, dist=dist))
+
+
 def batched_lp(n_inst: int, m_range=(1000, 50000), rho_range=(8.0, 30.0),
                seed_base: int = BASE_SEED + 1000, name="batched") -> LP:
     """n_inst independent Bernoulli LPs (the tiny-workload generator) packed block-diagonally:
@@ -378,6 +436,8 @@ WORKLOADS = {
     "zipf4m": "single larger sparse LP: m=2M, n=4M, same generator as zipf1m, FP32->FP64",
     "batch256": "batched: 256 Bernoulli LPs, m_i~U{1k..50k}, n_i=2m_i, 8-30 nnz/row",
     "transport10m": "transportation 2000 x 5000: n=10M, m=7000, FP32->FP64",
+    "qap40": "QAP LP relaxation (Section 4.4 form), N=40 random symmetric flow/distance "
+             "U{0..99}: n=2.56M, m=1.41M (all equality), nnz=7.81M, plain FP64",
 }
 
 
@@ -400,4 +460,7 @@ def make(name: str, scale: float = 1.0) -> LP:
         s = max(2, int(round(2000 * scale)))
         d = max(2, int(round(5000 * scale)))
         return transport_lp(s, d, seed=BASE_SEED + 4, name="transport10m")
+    if name == "qap40":  # scale acts on the nonzeros, which grow as N^4
+        N = max(3, int(round(40 * scale ** 0.25)))
+        return qap_lp(N, seed=BASE_SEED + 5, name="qap40")
     raise KeyError(name)

@@ -96,3 +96,7 @@ def test_fullsize_device_setup_matches_host(name):
     assert ah == ad and th == td
     for a, b in ((xh, xd), (yh, yd), (zh, zd)):
         assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_fullsize_qap40_fp64():
+    _single("qap40", 60, hprlp.FP64)
