@@ -35,7 +35,7 @@ class Opts(C.Structure):
                 ("power_max_iter", C.c_int), ("power_tol", C.c_double),
                 ("lambda_override", C.c_double), ("use_halpern", C.c_int),
                 ("rho", C.c_double), ("use_restart", C.c_int), ("sigma_update", C.c_int),
-                ("trace_every_iter", C.c_int)]
+                ("trace_every_iter", C.c_int), ("t1_zero", C.c_int)]
 
 
 class Result(C.Structure):
@@ -50,7 +50,8 @@ class Result(C.Structure):
 DEFAULTS = dict(tol=1e-8, check_every=150, max_iter=1_000_000, time_limit=0.0, alpha1=0.2,
                 alpha2=0.6, alpha3=0.2, sigma0=1.0, ruiz_iters=10, pock_chambolle=1,
                 normalize_bc=1, power_max_iter=5000, power_tol=1e-10, lambda_override=0.0,
-                use_halpern=1, rho=2.0, use_restart=1, sigma_update=1, trace_every_iter=0)
+                use_halpern=1, rho=2.0, use_restart=1, sigma_update=1, trace_every_iter=0,
+                t1_zero=0)
 
 
 def build(force: bool = False) -> str:

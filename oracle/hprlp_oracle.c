@@ -21,6 +21,13 @@
  *     primal_dual_infeasibility (Section 3.2)
  *   - termination: the three relative inequalities of Section 4.1, evaluated at w_bar on
  *     the original (unscaled) data, every check_every (=150) iterations
+ *   - option t1_zero, the choice T1 = 0 of Section 3.2 (item 1) for LPs without inequality
+ *     rows: the y-step is the exact minimiser, A A^T y_bar = (b - A(x_bar + sigma(z_bar -
+ *     c))) / sigma (eq. AATy=R), solved with a dense Cholesky factor of A~ A~^T.  Written
+ *     with the x-step it is y_bar = y + (A~A~^T)^{-1} (b~ - A~(2 x_bar - x)) / sigma.  M of
+ *     eq. def:M then has the block sigma A A^T, so ||d||_M^2 = sigma ||A~^T dy||^2 +
+ *     2 <dy, A~ dx> + ||dx||^2 / sigma, and SigmaUpdate uses eq. sigma_T1=0
+ *     (Delta_y = ||A~^T (y_bar - y0)||).  No lambda is needed.
  *
  * Readings where the paper is silent (kept identical in the GPU library):
  *   - R~_{r,0} is evaluated on the first iteration of every outer loop; the merit used by
@@ -62,6 +69,8 @@ typedef struct {
     int use_restart;       /* 1: restart criteria of Section 3.1                    */
     int sigma_update;      /* 1: SigmaUpdate (Algorithm 3); 0: sigma fixed          */
     int trace_every_iter;  /* 1: record merit and KKT residual after every iteration */
+    int t1_zero;           /* 1: T1 = 0 (Section 3.2, item 1); needs m2 = 0 and A of   */
+                           /*    full row rank                                          */
 } oracle_opts;
 
 typedef struct {
@@ -274,6 +283,51 @@ static void original_residuals(const problem *P, const double *xb, const double 
  * (merit ||w^k - w_hat^{k+1}||_M, ||R(w_bar^{k+1})|| on the scaled data, max bound
  * violation of x_bar, max cone violation of y_bar).
  */
+/* Dense lower Cholesky factor L (row-major m x m) of A~ A~^T.  Returns 0, or -7 when the
+ * matrix is not positive definite (A without full row rank). */
+static int gram_cholesky(long long m, long long n, const int64_t *rp, const int32_t *ci,
+                         const double *val, double *L) {
+    double *row = calloc(n, sizeof(double));
+    if (!row) return -6;
+    for (long long i = 0; i < m; ++i) {
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) row[ci[p]] = val[p];
+        for (long long k = 0; k <= i; ++k) {  /* (A A^T)_{ik} = <row i, row k> */
+            double acc = 0.0;
+            for (int64_t p = rp[k]; p < rp[k + 1]; ++p) acc += val[p] * row[ci[p]];
+            L[i * m + k] = acc;
+        }
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) row[ci[p]] = 0.0;
+    }
+    free(row);
+    for (long long j = 0; j < m; ++j) {  /* column by column, in place on the lower part */
+        double d = L[j * m + j];
+        for (long long k = 0; k < j; ++k) d -= L[j * m + k] * L[j * m + k];
+        if (!(d > 0.0)) return -7;
+        const double ljj = sqrt(d);
+        L[j * m + j] = ljj;
+        for (long long i = j + 1; i < m; ++i) {
+            double a = L[i * m + j];
+            for (long long k = 0; k < j; ++k) a -= L[i * m + k] * L[j * m + k];
+            L[i * m + j] = a / ljj;
+        }
+    }
+    return 0;
+}
+
+/* x := (L L^T)^{-1} x (forward, then backward substitution). */
+static void chol_solve(long long m, const double *L, double *x) {
+    for (long long i = 0; i < m; ++i) {
+        double a = x[i];
+        for (long long k = 0; k < i; ++k) a -= L[i * m + k] * x[k];
+        x[i] = a / L[i * m + i];
+    }
+    for (long long i = m - 1; i >= 0; --i) {
+        double a = x[i];
+        for (long long k = i + 1; k < m; ++k) a -= L[k * m + i] * x[k];
+        x[i] = a / L[i * m + i];
+    }
+}
+
 int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
                  const int32_t *ci, const double *val, const double *b, const double *c,
                  const double *l, const double *u, const oracle_opts *o, double *x_out,
@@ -319,7 +373,17 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
 
     double t0 = now_s();
     double lambda;
-    if (o->lambda_override > 0.0) {
+    double *Lc = NULL, *gt = NULL; /* T1 = 0: Cholesky factor of A~A~^T, and A~^T dy */
+    if (o->t1_zero) {
+        if (m2 != 0) return -1;
+        Lc = malloc(sizeof(double) * (size_t)(m * m));
+        gt = malloc(sizeof(double) * (size_t)n);
+        if (!Lc || !gt) return -6;
+        int rcc = gram_cholesky(m, n, rp, ci, val_s, Lc);
+        if (rcc) return rcc;
+        lambda = 0.0;  /* not used */
+        res->power_iters = 0;
+    } else if (o->lambda_override > 0.0) {
         lambda = o->lambda_override;
         res->power_iters = 0;
     } else {
@@ -350,10 +414,16 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
         }
         /* y-step (eq. update-y-2) with T1 = lambda I - A A^T */
         csr_mv(m, rp, ci, val_s, xr, s);
-        for (long long i = 0; i < m; ++i) {
-            double yi = y[i] + (b_s[i] - s[i]) / (lambda * sigma);
-            if (i >= m1 && yi < 0.0) yi = 0.0;
-            yb[i] = yi;
+        if (o->t1_zero) {  /* T1 = 0: exact minimiser (eq. AATy=R), no inequality rows */
+            for (long long i = 0; i < m; ++i) wm[i] = b_s[i] - s[i];
+            chol_solve(m, Lc, wm);
+            for (long long i = 0; i < m; ++i) yb[i] = y[i] + wm[i] / sigma;
+        } else {
+            for (long long i = 0; i < m; ++i) {
+                double yi = y[i] + (b_s[i] - s[i]) / (lambda * sigma);
+                if (i >= m1 && yi < 0.0) yi = 0.0;
+                yb[i] = yi;
+            }
         }
         /* reflection w_hat = rho w_bar + (1 - rho) w, and d = w - w_hat for the merit */
         for (long long j = 0; j < n; ++j) {
@@ -379,8 +449,14 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
             /* R~ = ||w - w_hat||_M, M of eq. def:M with T1 = lambda I - A A^T:
              * ||d||_M^2 = sigma lambda ||dy||^2 + 2 <dy, A dx> + ||dx||^2 / sigma */
             csr_mv(m, rp, ci, val_s, dx, s);
-            double q = sigma * lambda * dot(m, dy, dy) + 2.0 * dot(m, dy, s) +
-                       dot(n, dx, dx) / sigma;
+            double ty;  /* <dy, (T1 + A A^T) dy> */
+            if (o->t1_zero) {
+                csr_mtv(m, n, rp, ci, val_s, dy, gt);
+                ty = dot(n, gt, gt);
+            } else {
+                ty = lambda * dot(m, dy, dy);
+            }
+            double q = sigma * ty + 2.0 * dot(m, dy, s) + dot(n, dx, dx) / sigma;
             merit = sqrt(q > 0.0 ? q : 0.0);
         }
         if (o->trace_every_iter && iter_trace && nit < iter_cap) {
@@ -468,7 +544,12 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
             for (long long j = 0; j < n; ++j) wn[j] = xb[j] - x0[j];
             for (long long i = 0; i < m; ++i) wm[i] = yb[i] - y0[i];
             Dx = nrm2(n, wn);
-            Dy = sqrt(lambda) * nrm2(m, wm);
+            if (o->t1_zero) {  /* eq. sigma_T1=0 */
+                csr_mtv(m, n, rp, ci, val_s, wm, gt);
+                Dy = nrm2(n, gt);
+            } else {
+                Dy = sqrt(lambda) * nrm2(m, wm);
+            }
             csr_mv(m, rp, ci, val_s, xb, s);
             for (long long i = 0; i < m; ++i) wm[i] = b_s[i] - s[i];
             err_p = sqrt(proj_D_sq(m1, m, wm)) / (1.0 + bs_norm);
@@ -510,5 +591,6 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
     free(val_s); free(dr); free(dc); free(b_s); free(c_s); free(l_s); free(u_s);
     free(x); free(y); free(x0); free(y0); free(xb); free(yb); free(zb); free(v); free(g);
     free(s); free(xr); free(dx); free(dy); free(wm); free(wn); free(xo); free(yo); free(zo);
+    free(Lc); free(gt);
     return 0;
 }
