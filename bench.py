@@ -17,6 +17,8 @@ U{5..40}; Zipf(1.1) column popularity; plain FP64).  --config selects the other 
   transport10m  2000 x 5000 transportation LP (n = 10M), FP32 -> FP64
   qap40         LP relaxation of a random QAP with N = 40 in the form of Section 4.4
                 (n = 2.56M, m = 1.41M equality rows, nnz = 7.8M), FP64
+  ot4m          balanced optimal transport 2048 x 2048 (m = 4095 equality rows, n = 4.19M),
+                FP64; with --t1-zero the T1 = 0 variant of Section 3.2 (exact y-step)
 --compare adds the plain-FP64 GPU solver on the same instances under the same time budget:
 the FP64 single-LP solve for the mixed-precision workloads, and for batch256 the single-LP
 FP64 solver run on the instances one after another.
@@ -154,7 +156,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default="zipf1m",
-                    choices=["tiny", "zipf1m", "zipf4m", "batch256", "transport10m", "qap40"])
+                    choices=["tiny", "zipf1m", "zipf4m", "batch256", "transport10m", "qap40",
+                             "ot4m"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "fp64a32"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--time-limit", type=float, default=60.0, help="seconds per solve")
@@ -163,6 +166,8 @@ def main():
                     help="also run the plain-FP64 GPU solver on the same instances")
     ap.add_argument("--ablation", action="store_true",
                     help="run the ablation steps of Section 4.2 instead of the benchmark")
+    ap.add_argument("--t1-zero", action="store_true",
+                    help="the T1 = 0 variant (equality-only LPs, exact y-step through A A^T)")
     ap.add_argument("--setup-on-host", action="store_true",
                     help="preprocess on the host instead of the GPU (bit-identical arrays)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -199,7 +204,8 @@ def main():
     sampled = not (args.no_profile or batched or lp.nnz < 100_000)
     opts = dict(tol=args.tol, time_limit=args.time_limit, precision=P, check_every=ce,
                 profile=50 if sampled else 0, autotune=0 if args.no_autotune else 1,
-                setup_on_host=1 if args.setup_on_host else 0)
+                setup_on_host=1 if args.setup_on_host else 0,
+                t1_zero=1 if args.t1_zero else 0)
     t0 = time.perf_counter()
     solver = hprlp.Solver(lp, batched=batched, **opts)
     t_create = time.perf_counter() - t0
@@ -240,7 +246,7 @@ def main():
         "config": {"workload": lpgen.WORKLOADS[args.config], "name": args.config,
                    "m": lp.m, "m1": lp.m1, "n": lp.n, "nnz": lp.nnz, "precision": prec,
                    "tol": args.tol, "time_limit_s": args.time_limit, "check_every": ce,
-                   "autotune": not args.no_autotune},
+                   "autotune": not args.no_autotune, "t1_zero": bool(args.t1_zero)},
         "solved": solved, "status": st["status"], "iters": iters,
         "power_iters": int(st["power_iters"]), "restarts": int(st["restarts"]),
         "rel_kkt": max(st["rel_p"], st["rel_d"], st["rel_gap"]),
@@ -288,15 +294,19 @@ def main():
         if prec == "mixed" and st["iters_fp32"] < iters:
             s_vec = 8
             col_b, row_b = pass_bytes(lp.m, lp.n, lp.nnz, s_val, s_vec)
+    row_kernel = "k_pass<RowOp> (y-step over A)"
+    if args.t1_zero:  # residual pass over A, then the dense product with G = (A A^T)^-1
+        row_b += 8 * lp.m * lp.m
+        row_kernel = "k_t1_resid + k_t1_solve (T1 = 0 y-step: residual over A, G r)"
     col_gbs = col_b / (col_ms * 1e-3) / 1e9
     row_gbs = row_b / (row_ms * 1e-3) / 1e9
     dom = "col" if col_ms >= row_ms else "row"
     ach = col_gbs if dom == "col" else row_gbs
     out["roofline"] = {
         "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-        "frac": ach / PEAK_HBM_GBS, "traffic": read_traffic(dom, args.config),
-        "kernel": ("k_pass<ColOp> (x-step over A^T)" if dom == "col"
-                   else "k_pass<RowOp> (y-step over A)"),
+        "frac": ach / PEAK_HBM_GBS,
+        "traffic": None if args.t1_zero and dom == "row" else read_traffic(dom, args.config),
+        "kernel": ("k_pass<ColOp> (x-step over A^T)" if dom == "col" else row_kernel),
         "alg_bytes_per_launch": col_b if dom == "col" else row_b,
         "avg_launch_ms": col_ms if dom == "col" else row_ms, "timing": timing,
     }

@@ -115,6 +115,13 @@ typedef struct {
     double rho;              /* relaxation of Algorithm 2: w_hat = rho w_bar + (1-rho) w,   */
                              /* in (0, 2]; 2 (default) = Peaceman-Rachford (HPR), 1 =        */
                              /* Douglas-Rachford (the paper's ablation, Section 4.2)         */
+    int t1_zero;             /* 1: the T1 = 0 variant of Section 3.2 for LPs without        */
+                             /* inequality rows (m2 = 0): the y-step solves with A A^T      */
+                             /* exactly (eq. AATy=R) through a dense inverse of A~A~^T      */
+                             /* formed at create (m <= 4096, A of full row rank, FP64,      */
+                             /* single LPs; EINVAL / EDIM otherwise), sigma by eq.          */
+                             /* sigma_T1=0; no power method.  0 (default): T1 = lambda I -  */
+                             /* A A^T                                                        */
     int setup_on_host;       /* 0 (default): create renumbers, transposes and scales the    */
                              /* problem on the GPU, in scratch inside the workspace (which  */
                              /* hprlp_workspace_bytes then includes); 1: on the host, with  */

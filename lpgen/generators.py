@@ -291,6 +291,35 @@ def transport_lp(n_src: int, n_dst: int, seed: int, name="transport") -> LP:
                         supply_factor=k))
 
 
+def ot_lp(n_src: int, n_dst: int, seed: int, name="ot") -> LP:
+    """Balanced optimal-transport LP, every row an equality: flow x_ij at column
+    i n_dst + j, supply rows sum_j x_ij = s_i for every i, then demand rows sum_i x_ij = d_j
+    for j < n_dst - 1 (the last one follows from the others, so A has full row rank).
+    Sources and sinks are uniform points in the unit square; cost 100 |p_i - q_j|^2 rounded
+    to FP32; integer weights U{1..100}, supplies scaled by the total demand and demands by
+    the total supply so both sum to the same value; x >= 0."""
+    rng = np.random.default_rng(seed)
+    p, q = rng.random((n_src, 2)), rng.random((n_dst, 2))
+    sw = rng.integers(1, 101, n_src).astype(np.float64)
+    dw = rng.integers(1, 101, n_dst).astype(np.float64)
+    sup, dem = sw * dw.sum(), dw * sw.sum()
+    n = n_src * n_dst
+    cost = (100.0 * ((p[:, None, :] - q[None, :, :]) ** 2).sum(-1)).ravel()
+    cost = cost.astype(np.float32).astype(np.float64)
+    nd = n_dst - 1
+    sup_rowptr = np.arange(n_src + 1, dtype=np.int64) * n_dst
+    dem_rowptr = n + np.arange(nd + 1, dtype=np.int64) * n_src
+    rowptr = np.concatenate([sup_rowptr, dem_rowptr[1:]])
+    sup_cols = np.arange(n, dtype=np.int64)
+    dem_cols = (np.arange(n_src, dtype=np.int64)[None, :] * n_dst
+                + np.arange(nd, dtype=np.int64)[:, None]).ravel()
+    col = np.concatenate([sup_cols, dem_cols]).astype(np.int32)
+    m = n_src + nd
+    return LP(name, m, 0, n, rowptr, col, np.ones(len(col)), np.concatenate([sup, dem[:nd]]),
+              cost, np.zeros(n), np.full(n, np.inf), None,
+              meta=dict(family="ot", n_src=n_src, n_dst=n_dst, seed=seed))
+
+
 def qap_lp(N: int, seed: int, name="qap") -> LP:
     """LP relaxation of a quadratic assignment problem, in the form of the paper's large QAP
     experiments (Section 4.4, Adams-Johnson linearisation), every index running over 1..N.
@@ -436,6 +465,8 @@ WORKLOADS = {
     "zipf4m": "single larger sparse LP: m=2M, n=4M, same generator as zipf1m, FP32->FP64",
     "batch256": "batched: 256 Bernoulli LPs, m_i~U{1k..50k}, n_i=2m_i, 8-30 nnz/row",
     "transport10m": "transportation 2000 x 5000: n=10M, m=7000, FP32->FP64",
+    "ot4m": "balanced optimal transport 2048 x 2048 (all equality rows, last demand row "
+            "dropped): n=4.19M, m=4095, nnz=8.39M, plain FP64",
     "qap40": "QAP LP relaxation (Section 4.4 form), N=40 random symmetric flow/distance "
              "U{0..99}: n=2.56M, m=1.41M (all equality), nnz=7.81M, plain FP64",
 }
@@ -460,6 +491,9 @@ def make(name: str, scale: float = 1.0) -> LP:
         s = max(2, int(round(2000 * scale)))
         d = max(2, int(round(5000 * scale)))
         return transport_lp(s, d, seed=BASE_SEED + 4, name="transport10m")
+    if name == "ot4m":
+        k = max(2, int(round(2048 * scale ** 0.5)))
+        return ot_lp(k, k, seed=BASE_SEED + 6, name="ot4m")
     if name == "qap40":  # scale acts on the nonzeros, which grow as N^4
         N = max(3, int(round(40 * scale ** 0.25)))
         return qap_lp(N, seed=BASE_SEED + 5, name="qap40")

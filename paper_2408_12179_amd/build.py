@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build", "hprlp")
 LIB = os.path.join(PKG, "libhprlp.so")
-SOURCES = ["kernels.hip", "prep.hip", "setup.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "prep.hip", "t1zero.hip", "setup.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HPRLP_ARCH", "gfx950")

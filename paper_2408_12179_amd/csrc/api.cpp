@@ -64,6 +64,13 @@ constexpr int kTuneMinChunk = 2048, kTuneMinSplit = 2048;
 constexpr int64_t kTuneMinNnz = 100000;  // below this a pass is launch-bound: keep the defaults
 constexpr int kTuneReps = 10;
 
+// T1 = 0 variant: dense inverse of A~A~^T and its scratch.
+struct T1Dev {
+    double *F = nullptr, *LT = nullptr, *G = nullptr;  // [m][m] each
+    double *r = nullptr, *d0 = nullptr, *dd = nullptr; // [m]
+    double *parts = nullptr;                           // [t1_parts_len()]
+};
+
 // Device arrays of a batched solve (one entry per instance unless noted).
 struct BatchDev {
     double *sigma = nullptr, *lam = nullptr, *merit0 = nullptr, *merit_prev = nullptr;
@@ -127,6 +134,7 @@ struct hprlp_handle {
     double t_setup_ms = 0.0;                  // duration of create
     double t_prep_ms = 0.0, t_tune_ms = 0.0;  // create: preprocessing, schedule autotuning
     PrepScratch prep;                         // device preprocessing scratch (create only)
+    T1Dev t1;                                 // T1 = 0: inverse of A~A~^T
     // solve state (single LP)
     int prec = 0;
     long long t = 0, k = 0, r = 0;
@@ -163,6 +171,7 @@ struct Plan {
     int n_inst;
     bool batched;
     bool prep = false;   // scratch of the device preprocessing
+    int64_t t1m = 0;     // T1 = 0: rows of the dense inverse of A~A~^T (0: off)
 };
 
 void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
@@ -247,6 +256,13 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         b.active = cv.arr<int>(1);
         b.inv_norm = inv_norm;
     }
+    T1Dev t1;
+    if (p.t1m > 0) {
+        const size_t mm = (size_t)p.t1m * (size_t)p.t1m;
+        t1.F = cv.arr<double>(mm); t1.LT = cv.arr<double>(mm); t1.G = cv.arr<double>(mm);
+        t1.r = cv.arr<double>(m); t1.d0 = cv.arr<double>(m); t1.dd = cv.arr<double>(m);
+        t1.parts = cv.arr<double>(t1_parts_len());
+    }
     PrepScratch ps;
     if (p.prep) {  // last: nothing of the solve lives after it
         for (auto &b2 : ps.u) b2 = cv.arr<uint32_t>(nnz);
@@ -271,6 +287,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     }
     if (h) {
         h->prep = ps;
+        h->t1 = t1;
         h->A.rp = A.rp; h->A.ci = A.ci; h->A.va = A.va; h->A.items = A.items;
         h->A.splits = A.splits; h->A.split_part = A.split_part;
         h->T.rp = T.rp; h->T.ci = T.ci; h->T.va = T.va; h->T.items = T.items;
@@ -317,6 +334,7 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n
     p.n_inst = n_inst;
     p.batched = batched;
     p.prep = !o.setup_on_host;
+    p.t1m = (o.t1_zero && !batched) ? m : 0;
     return p;
 }
 
@@ -659,6 +677,38 @@ int validate_layout(const Layout &L, int64_t m, int64_t n, const int64_t *rowptr
 int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
                    const int32_t *inst_row, const int32_t *inst_col);
 
+// Where the T1 = 0 variant applies: one LP, equality rows only, FP64, a dense inverse of
+// A~A~^T of at most kT1MaxRows rows.
+int t1_check(const hprlp_options &o, bool batched, int64_t m, int64_t m2, std::string &err) {
+    if (!o.t1_zero) return HPRLP_OK;
+    if (batched) { err = "t1_zero applies to single LPs"; return HPRLP_EINVAL; }
+    if (m2 != 0) { err = "t1_zero needs an LP without inequality rows (m2 = 0)"; return HPRLP_EINVAL; }
+    if (o.precision != HPRLP_FP64) { err = "t1_zero runs in FP64 only"; return HPRLP_EINVAL; }
+    if (m > kT1MaxRows) {
+        err = "t1_zero: at most " + std::to_string(kT1MaxRows) + " rows (dense inverse of A A^T)";
+        return HPRLP_EDIM;
+    }
+    return HPRLP_OK;
+}
+
+// Build G = (A~A~^T)^{-1} and reject A without full row rank (a pivot of LDL^T at most
+// 1e-10 times its diagonal entry of A~A~^T).
+int t1_setup(hprlp_handle *h) {
+    const int m = (int)h->m;
+    HIPCHK(h, t1_build_inverse(h->A, h->T, m, h->t1.F, h->t1.LT, h->t1.G, h->t1.d0, h->t1.dd,
+                               h->st));
+    std::vector<double> d0((size_t)m), dd((size_t)m);
+    int rc;
+    if ((rc = download(h, d0.data(), h->t1.d0, (size_t)m)) ||
+        (rc = download(h, dd.data(), h->t1.dd, (size_t)m)))
+        return rc;
+    for (int k = 0; k < m; ++k)
+        if (!(dd[k] > 1e-10 * d0[k]) || !std::isfinite(dd[k]))
+            return fail(h, HPRLP_EINVAL, "t1_zero needs A of full row rank: A A^T is singular "
+                                         "(LDL^T pivot " + std::to_string(k) + ")");
+    return HPRLP_OK;
+}
+
 // Shared body of hprlp_create and hprlp_create_batched.
 int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
                 const int32_t *colidx, const double *val, const double *b, const double *c,
@@ -680,6 +730,8 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     const int64_t m = L.row_off[L.n_inst], n = L.col_off[L.n_inst];
     int64_t m1tot = 0;
     for (int bi = 0; bi < L.n_inst; ++bi) m1tot += L.m1[bi];
+    if ((rc = t1_check(o, L.batched, m, m - m1tot, err))) return fail(nullptr, rc, err);
+    if (o.t1_zero) o.graph = 0;  // the chunk graphs capture the lambda-variant passes
     rc = validate_problem(L.batched ? m : L.m1[0], L.batched ? 0 : m - L.m1[0], n, rowptr,
                           colidx, val, b, c, l, u, o, err);
     if (rc) return fail(nullptr, rc, err);
@@ -859,6 +911,7 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
         h->bsnorm = cst[0][4];
         h->csnorm = cst[0][5];
     }
+    if (!rc && o.t1_zero) rc = t1_setup(h);
     h->t_prep_ms = now_ms() - t_prep;
     const double t_tune = now_ms();
     if (!rc && o.autotune && nnz >= kTuneMinNnz)
@@ -945,11 +998,16 @@ int workspace_impl(int32_t n_inst, int64_t m, int64_t n, int64_t nnz, const hprl
 extern "C" int hprlp_workspace_bytes(int64_t m1, int64_t m2, int64_t n, int64_t nnz,
                                      const hprlp_options *opt, size_t *bytes) {
     if (m1 < 0 || m2 < 0) return fail(nullptr, HPRLP_EDIM, "bad dimensions");
+    if (opt) {
+        std::string err;
+        if (int rc = t1_check(*opt, false, m1 + m2, m2, err)) return fail(nullptr, rc, err);
+    }
     return workspace_impl(1, m1 + m2, n, nnz, opt, bytes, false);
 }
 
 extern "C" int hprlp_workspace_bytes_batched(int32_t n_inst, int64_t m, int64_t n, int64_t nnz,
                                              const hprlp_options *opt, size_t *bytes) {
+    if (opt && opt->t1_zero) return fail(nullptr, HPRLP_EINVAL, "t1_zero applies to single LPs");
     return workspace_impl(n_inst, m, n, nnz, opt, bytes, true);
 }
 
@@ -1035,6 +1093,15 @@ struct ProfRec {
 };
 
 // One iteration (column pass then row pass).  keep: also store w_bar and d = w - w_hat.
+// y-step of one iteration: the row pass (eq. update-y-2), or with T1 = 0 the exact solve
+hipError_t row_step(hprlp_handle *h, bool keep, const IterScalars &s, const void *vs,
+                    hipEvent_t em) {
+    if (!h->opt.t1_zero) return launch_row_pass(h->prec, keep, h->A, vs, s, h->st, em);
+    hipError_t e = t1_row_step(h->A, h->v64, s, h->t1.G, h->t1.r, (int)h->m, keep, h->st);
+    if (e == hipSuccess && em) e = hipEventRecord(em, h->st);
+    return e;
+}
+
 int run_iteration(hprlp_handle *h, bool keep, std::vector<ProfRec> *prof, size_t *ev_next) {
     IterScalars s;
     fill_scalars(h, s);
@@ -1051,7 +1118,7 @@ int run_iteration(hprlp_handle *h, bool keep, std::vector<ProfRec> *prof, size_t
             HIPCHK(h, hipEventRecord(e0, h->st));
         }
         hipError_t e = pass == 0 ? launch_col_pass(h->prec, keep, h->T, vs, s, h->st, em)
-                                 : launch_row_pass(h->prec, keep, h->A, vs, s, h->st, em);
+                                 : row_step(h, keep, s, vs, em);
         if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("pass launch: ") + hipGetErrorString(e));
         if (prof) HIPCHK(h, hipEventRecord(e1, h->st));
     }
@@ -1068,6 +1135,13 @@ int run_check(hprlp_handle *h, int slot) {
     if (e == hipSuccess)
         e = launch_check_col(h->prec, h->T, cur_set(h), h->chk, h->v64.cd, h->v64.sc, h->partsT,
                              outc, h->st);
+    if (e == hipSuccess && h->opt.t1_zero) {
+        // T1 = 0: the y block of M is sigma A~A~^T, so the merit's ||dy||^2 becomes
+        // ||A~^T dy||^2, and Delta_y of eq. sigma_T1=0 is ||A~^T (y_bar - y0)|| (lambda = 1)
+        e = t1_atv_sq(h->T, (int)h->n, h->v64.dy, nullptr, h->t1.parts, outr + 3, h->st);
+        if (e == hipSuccess)
+            e = t1_atv_sq(h->T, (int)h->n, h->v64.ybar, h->v64.y0, h->t1.parts, outr + 5, h->st);
+    }
     if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("check launch: ") + hipGetErrorString(e));
     return HPRLP_OK;
 }
@@ -1483,7 +1557,9 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
     h->sigma = o.sigma0;
     int rc;
     int piters = 0;
-    if (o.lambda_override > 0) {
+    if (o.t1_zero) {
+        h->lambda = 1.0;  // no lambda in this variant; 1 leaves the merit and Delta_y as above
+    } else if (o.lambda_override > 0) {
         h->lambda = o.lambda_override;
     } else {
         std::vector<double> lam;
@@ -1647,7 +1723,7 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
     s.status = st_out;
     s.power_iters = piters;
     s.sigma = h->sigma;
-    s.lambda = h->lambda;
+    s.lambda = o.t1_zero ? 0.0 : h->lambda;
     s.beta_b = h->beta_b;
     s.beta_c = h->beta_c;
     s.t_power_ms = t_power;
@@ -2074,7 +2150,8 @@ extern "C" int hprlp_time_passes(hprlp_handle *h, int reps, double *col_ms, doub
     HIPCHK(h, hipEventRecord(e[1], h->st));
     HIPCHK(h, hipEventRecord(e[2], h->st));
     for (int i = 0; i < reps; ++i) {
-        hipError_t r = launch_row_pass(h->prec, false, h->A, vs, s, h->st, nullptr, pba);
+        hipError_t r = h->batched ? launch_row_pass(h->prec, false, h->A, vs, s, h->st, nullptr, pba)
+                                  : row_step(h, false, s, vs, nullptr);
         if (r != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(r));
     }
     HIPCHK(h, hipEventRecord(e[3], h->st));

@@ -212,6 +212,22 @@ hipError_t prep_vectors(const PrepArgs &a, const int *row_off, const int *col_of
                         const double *cst, const VecSet<double> &d, const VecSet<float> &f,
                         const CheckData &c, double *ux, double *uy, hipStream_t st);
 
+// ---------------------------------------------------------------- T1 = 0 (t1zero.hip)
+// Section 3.2, item 1: LPs without inequality rows, y-step solved exactly through the
+// dense inverse G of A~A~^T (at most kT1MaxRows rows).
+constexpr int kT1MaxRows = 4096;
+size_t t1_parts_len();
+// G = (A~A~^T)^{-1} via LDL^T; F, LT: m*m scratch; diag0 / diagd: the diagonal of A~A~^T
+// and the LDL^T pivots (for the rank check on the host)
+hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, double *LT,
+                            double *G, double *diag0, double *diagd, hipStream_t st);
+// y-step: r = b~ - A~ x_hat, then y_bar = y + (G r) / sigma and the y update of Algorithm 2
+hipError_t t1_row_step(const DevMat &A, const VecSet<double> &v, const IterScalars &s,
+                       const double *G, double *r, int m, bool keep, hipStream_t st);
+// *out = ||A~^T (va - vb)||^2 (vb nullable); parts: t1_parts_len() doubles
+hipError_t t1_atv_sq(const DevMat &T, int n, const double *va, const double *vb, double *parts,
+                     double *out, hipStream_t st);
+
 // vector utilities
 hipError_t launch_fill(double *p, long long n, double v, hipStream_t st);
 hipError_t launch_fill_f(float *p, long long n, float v, hipStream_t st);

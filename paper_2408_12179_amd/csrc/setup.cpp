@@ -94,7 +94,8 @@ int validate_options(const hprlp_options &o, std::string &err) {
               o.tile_rows <= kMaxTileRows &&
               o.short_max >= 1 && o.short_max <= o.tile_nnz &&
               o.split_len >= o.short_max && o.chunk_nnz >= 256 && o.stall_ratio > 0 &&
-              o.stall_ratio <= 1 && o.rho > 0 && o.rho <= 2;
+              o.stall_ratio <= 1 && o.rho > 0 && o.rho <= 2 &&
+              (o.t1_zero == 0 || o.t1_zero == 1) && (o.setup_on_host == 0 || o.setup_on_host == 1);
     if (!ok) err = "invalid option value";
     return ok ? HPRLP_OK : HPRLP_EINVAL;
 }

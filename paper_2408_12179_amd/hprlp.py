@@ -46,7 +46,8 @@ class Options(C.Structure):
                 ("tile_rows", C.c_int), ("short_max", C.c_int), ("split_len", C.c_int),
                 ("chunk_nnz", C.c_int), ("reorder", C.c_int), ("profile", C.c_int),
                 ("verbose", C.c_int), ("autotune", C.c_int), ("stall_ratio", C.c_double),
-                ("graph", C.c_int), ("rho", C.c_double), ("setup_on_host", C.c_int)]
+                ("graph", C.c_int), ("rho", C.c_double), ("t1_zero", C.c_int),
+                ("setup_on_host", C.c_int)]
 
 
 class Stats(C.Structure):

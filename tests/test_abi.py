@@ -257,3 +257,24 @@ def test_device_setup_scratch_is_in_the_workspace(lib):
                                        hprlp.default_options(precision=hprlp.MIXED,
                                                              setup_on_host=1))
     assert mixed - mixed_host >= 48 * nnz
+
+
+def test_t1_zero_limits(lib):
+    o = hprlp.default_options(t1_zero=1)
+    assert hprlp.workspace_bytes(100, 0, 400, 2000, o) > hprlp.workspace_bytes(
+        100, 0, 400, 2000, hprlp.default_options()) + 3 * 8 * 100 * 100 - 1
+    with pytest.raises(hprlp.HPRLPError) as e:
+        hprlp.workspace_bytes(100, 5, 400, 2000, o)  # inequality rows
+    assert e.value.code == hprlp.EINVAL
+    with pytest.raises(hprlp.HPRLPError) as e:
+        hprlp.workspace_bytes(5000, 0, 40000, 200000, o)  # beyond the dense inverse
+    assert e.value.code == hprlp.EDIM
+    with pytest.raises(hprlp.HPRLPError) as e:
+        hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=1,
+                                                                       precision=hprlp.MIXED))
+    assert e.value.code == hprlp.EINVAL
+    with pytest.raises(hprlp.HPRLPError) as e:
+        hprlp.workspace_bytes_batched(2, 100, 400, 2000, o)
+    assert e.value.code == hprlp.EINVAL
+    with pytest.raises(hprlp.HPRLPError):
+        hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=2))

@@ -95,3 +95,26 @@ def test_t1zero_rejects_inequality_rows(oracle_mod):
     lp = lpgen.bernoulli_lp(10, 5, 40, 0.2, seed=320)
     with pytest.raises(RuntimeError):
         oracle_mod.solve(lp, t1_zero=1)
+
+
+@pytest.mark.parametrize("ns,nd", [(5, 7), (12, 15)])
+def test_ot_generator_full_rank_and_feasible_coupling(ns, nd):
+    lp = lpgen.ot_lp(ns, nd, seed=ns)
+    A = _dense(lp)
+    assert lp.m == ns + nd - 1 and lp.m2 == 0 and np.linalg.matrix_rank(A) == lp.m
+    s, d = lp.b[:ns], np.concatenate([lp.b[ns:], [0.0]])
+    d[-1] = s.sum() - d[:-1].sum()
+    assert d[-1] > 0 and np.all(d > 0)
+    x = (s[:, None] * d[None, :] / s.sum()).ravel()  # independent coupling
+    assert np.allclose(A @ x, lp.b, rtol=1e-12)
+
+
+def test_oracle_t1zero_on_ot_matches_highs(oracle_mod):
+    from scipy.optimize import linprog
+    import scipy.sparse as sp
+    lp = lpgen.ot_lp(12, 15, seed=3)
+    r = oracle_mod.solve(lp, t1_zero=1)
+    assert r.status == "OPTIMAL"
+    A = sp.csr_matrix((lp.val, lp.colidx, lp.rowptr), shape=(lp.m, lp.n))
+    h = linprog(lp.c, A_eq=A, b_eq=lp.b, bounds=(0, None), method="highs")
+    assert h.status == 0 and abs(r.pobj - h.fun) <= 1e-7 * (1 + abs(h.fun))
