@@ -1373,25 +1373,37 @@ int install_schedule(hprlp_handle *h, bool col, Schedule &&S) {
 
 // Mean duration (ms) of one launch of the row pass (col = false) or column pass, over
 // kTuneReps launches after two warm-up launches, bracketed by HIP events.
+// Time one pass as a solve runs it: every launch follows a launch of the other pass (the
+// two matrices together outgrow the infinity cache, so back-to-back launches of one pass
+// would find its matrix cached).  2 warm-up pairs, then kTuneReps pairs with HIP events
+// around the pass being timed; the result is the mean of those launches.
 int time_pass(hprlp_handle *h, bool col, double *ms) {
     IterScalars s;
     fill_scalars(h, s);
     const BatchArgs ba = batch_args(h, 0);
     const BatchArgs *pba = h->batched ? &ba : nullptr;
     const void *vs = cur_set(h);
-    hipEvent_t e0 = pool_event(h, 0), e1 = pool_event(h, 1);
-    if (!e0 || !e1) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
+    for (int i = 0; i < 2 * kTuneReps; ++i)
+        if (!pool_event(h, (size_t)i)) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
     for (int i = 0; i < 2 + kTuneReps; ++i) {
-        if (i == 2) HIPCHK(h, hipEventRecord(e0, h->st));
-        const hipError_t e = col ? launch_col_pass(h->prec, false, h->T, vs, s, h->st, nullptr, pba)
-                                 : launch_row_pass(h->prec, false, h->A, vs, s, h->st, nullptr, pba);
-        if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("pass launch: ") + hipGetErrorString(e));
+        for (int which = 0; which < 2; ++which) {
+            const bool c = which == 0 ? !col : col;  // the other pass, then the timed one
+            const bool timed = which == 1 && i >= 2;
+            if (timed) HIPCHK(h, hipEventRecord(h->ev_pool[2 * (i - 2)], h->st));
+            const hipError_t e = c ? launch_col_pass(h->prec, false, h->T, vs, s, h->st, nullptr, pba)
+                                   : launch_row_pass(h->prec, false, h->A, vs, s, h->st, nullptr, pba);
+            if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("pass launch: ") + hipGetErrorString(e));
+            if (timed) HIPCHK(h, hipEventRecord(h->ev_pool[2 * (i - 2) + 1], h->st));
+        }
     }
-    HIPCHK(h, hipEventRecord(e1, h->st));
-    HIPCHK(h, hipEventSynchronize(e1));
-    float t = 0.f;
-    HIPCHK(h, hipEventElapsedTime(&t, e0, e1));
-    *ms = (double)t / kTuneReps;
+    HIPCHK(h, hipEventSynchronize(h->ev_pool[2 * kTuneReps - 1]));
+    double total = 0.0;
+    for (int i = 0; i < kTuneReps; ++i) {
+        float t = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&t, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]));
+        total += t;
+    }
+    *ms = total / kTuneReps;
     return HPRLP_OK;
 }
 
