@@ -285,7 +285,10 @@ def main():
     if st["col_pass_launches"] > 0:
         col_ms = st["col_pass_ms"] / st["col_pass_launches"]
         row_ms = st["row_pass_ms"] / st["row_pass_launches"]
-        split_pi = st["split_ms"] / max(st["col_pass_launches"], 1)
+        # time between the main kernel's end event and the pass's end event: the split-row
+        # finisher where a schedule has split rows, otherwise just the event gap
+        has_split = sched["A"]["chunks"] > 0 or sched["AT"]["chunks"] > 0
+        split_pi = st["split_ms"] / max(st["col_pass_launches"], 1) if has_split else None
         timing = "HIP events around every 50th iteration's passes inside the timed solve"
     else:
         col_ms, row_ms = solver.time_passes(20)
