@@ -100,3 +100,23 @@ def test_fullsize_device_setup_matches_host(name):
 
 def test_fullsize_qap40_fp64():
     _single("qap40", 60, hprlp.FP64)
+
+
+def test_fullsize_ot4m_t1zero_first_y_step():
+    """T1 = 0 at full size (m = 4095): after one iteration from the origin (sigma = 1) the
+    GPU's y_bar solves eq. AATy=R, A~A~^T y_bar = b~ - 2 A~ x_bar, checked with scipy."""
+    import scipy.sparse as sp
+    lp = lpgen.make("ot4m")
+    s = hprlp.Solver(lp, t1_zero=1, max_iter=1)
+    sol = s.solve()
+    dr, dc = s.iterate(hprlp.DROW), s.iterate(hprlp.DCOL)
+    bb, bc = sol.stats["beta_b"], sol.stats["beta_c"]
+    A = sp.csr_matrix((lp.val, lp.colidx, lp.rowptr), shape=(lp.m, lp.n))
+    At = sp.diags(dr) @ A @ sp.diags(dc)
+    xb = sol.x / (bb * dc)
+    yb = sol.y / (bc * dr)
+    lhs = At @ (At.T @ yb)
+    rhs = dr * lp.b / bb - 2.0 * (At @ xb)
+    assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs), \
+        np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs)
+    s.close()

@@ -102,3 +102,16 @@ def test_t1zero_deterministic():
     b = hprlp.Solver(lp, t1_zero=1, max_iter=500).solve()
     for u, v in ((a.x, b.x), (a.y, b.y), (a.z, b.z)):
         assert np.array_equal(u.view(np.uint64), v.view(np.uint64))
+
+
+def test_t1zero_parity_ot_512():
+    """m = 1023: the dense inverse spans many 16- and 64-wide tiles with ragged edges."""
+    lp = lpgen.ot_lp(512, 512, seed=506)
+    ref = oracle.solve(lp, t1_zero=1, max_iter=100)
+    s = hprlp.Solver(lp, t1_zero=1, max_iter=100)
+    sol = s.solve()
+    assert sol.stats["iters"] == ref.iters == 100
+    for k, a, b in (("x", sol.x, ref.x), ("y", sol.y, ref.y), ("z", sol.z, ref.z),
+                    ("y_cur", s.iterate(hprlp.YCUR), ref.y_cur)):
+        assert rel(a, b) <= 1e-10, (k, rel(a, b))
+    s.close()
