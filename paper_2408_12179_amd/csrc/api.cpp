@@ -11,11 +11,13 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hprlp_internal.h"
@@ -1444,36 +1446,62 @@ int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
             return (int)S.items.size() <= cap[0] && (int)S.splits.size() <= cap[1] &&
                    S.n_chunk_slots <= cap[2];
         };
-        auto try_p = [&](const ScheduleParams &p) -> int {
-            if (p.short_max > p.tile_nnz || p.split_len < p.short_max) return HPRLP_OK;
-            Schedule S;
-            build_schedule(rows, rp, p, inst, S);
-            if (!cap_ok(S) || same_schedule(S, best_s)) return HPRLP_OK;
-            Schedule keep = S;
-            int r2 = install_schedule(h, col, std::move(S));
-            if (r2) return r2;
-            double ms = 0.0;
-            if ((r2 = time_pass(h, col, &ms))) return r2;
-            if (ms < 0.97 * best_ms) {
-                best_ms = ms;
-                best = p;
-                best_s = std::move(keep);
+        // One coordinate of the descent: the candidate schedules are built on host threads
+        // (pure functions of the row pointers), then installed and timed one by one.
+        auto sweep = [&](const std::vector<ScheduleParams> &cands) -> int {
+            std::vector<Schedule> built(cands.size());
+            std::vector<char> ok(cands.size(), 0);
+            std::atomic<size_t> next{0};
+            auto worker = [&]() {
+                for (size_t c; (c = next.fetch_add(1)) < cands.size();) {
+                    const ScheduleParams &p = cands[c];
+                    if (p.short_max > p.tile_nnz || p.split_len < p.short_max) continue;
+                    build_schedule(rows, rp, p, inst, built[c]);
+                    ok[c] = 1;
+                }
+            };
+            const size_t nt = std::min<size_t>(cands.size(), 8);
+            std::vector<std::thread> pool;
+            for (size_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+            worker();
+            for (auto &t : pool) t.join();
+            for (size_t c = 0; c < cands.size(); ++c) {
+                if (!ok[c] || !cap_ok(built[c]) || same_schedule(built[c], best_s)) continue;
+                Schedule keep = built[c];
+                int r2 = install_schedule(h, col, std::move(built[c]));
+                if (r2) return r2;
+                double ms = 0.0;
+                if ((r2 = time_pass(h, col, &ms))) return r2;
+                if (ms < 0.97 * best_ms) {
+                    best_ms = ms;
+                    best = cands[c];
+                    best_s = std::move(keep);
+                }
             }
             return HPRLP_OK;
         };
-        for (int tn : kTuneTileNnz)
-            for (int tr : kTuneTileRows)
-                if ((rc = try_p({tn, tr, std::min(best.short_max, tn), best.split_len, best.chunk_nnz})))
-                    return rc;
-        const ScheduleParams shape = best;
-        for (int sm : kTuneShortMax)
-            if ((rc = try_p({shape.tile_nnz, shape.tile_rows, sm, std::max(shape.split_len, sm), shape.chunk_nnz})))
-                return rc;
+        {
+            const ScheduleParams b0 = best;
+            std::vector<ScheduleParams> c;
+            for (int tn : kTuneTileNnz)
+                for (int tr : kTuneTileRows)
+                    c.push_back({tn, tr, std::min(b0.short_max, tn), b0.split_len, b0.chunk_nnz});
+            if ((rc = sweep(c))) return rc;
+        }
+        {
+            const ScheduleParams shape = best;
+            std::vector<ScheduleParams> c;
+            for (int sm : kTuneShortMax)
+                c.push_back({shape.tile_nnz, shape.tile_rows, sm, std::max(shape.split_len, sm),
+                             shape.chunk_nnz});
+            if ((rc = sweep(c))) return rc;
+        }
         if (maxlen > kTuneMinSplit) {
             const ScheduleParams sh = best;
+            std::vector<ScheduleParams> c;
             for (int sl : kTuneSplitLen)
-                for (int ch : kTuneChunk)
-                    if ((rc = try_p({sh.tile_nnz, sh.tile_rows, sh.short_max, sl, ch}))) return rc;
+                for (int ch : kTuneChunk) c.push_back({sh.tile_nnz, sh.tile_rows, sh.short_max, sl, ch});
+            if ((rc = sweep(c))) return rc;
         }
         if ((rc = install_schedule(h, col, std::move(best_s)))) return rc;
         (col ? h->spT : h->spA) = best;
