@@ -176,10 +176,14 @@ int hprlp_workspace_bytes(int64_t m1, int64_t m2, int64_t n, int64_t nnz,
 
 /* Validate and preprocess one LP (eq. primalLP) and upload it into d_workspace:
  *   - validation (see hprlp_err), done before any HIP call;
- *   - preconditioning on the host: 10 Ruiz passes, one Pock-Chambolle alpha=1 pass,
- *     b/c normalisation (Section 4.1, "Presolve and preconditioning");
- *   - CSR(A) and a stored CSR(A^T), so neither sparse product needs atomics;
- *   - the row-length tile schedules of both matrices.
+ *   - the column renumbering, CSR(A) and a stored CSR(A^T) (so neither sparse product
+ *     needs atomics), and the preconditioning: 10 Ruiz passes, one Pock-Chambolle
+ *     alpha=1 pass, b/c normalisation (Section 4.1, "Presolve and preconditioning"); on
+ *     the GPU inside the workspace, or on the host with setup_on_host = 1;
+ *   - the row-length tile schedules of both matrices (host), the autotuner's choice
+ *     among them (autotune = 1), and with t1_zero the dense inverse of A~A~^T.
+ * Errors after validation: EHIP (a HIP call failed), EINVAL (workspace too small, or
+ * t1_zero with A of deficient row rank).
  * m1 >= 0 equality rows, m2 >= 0 inequality rows, m1 + m2 >= 1, n >= 1, nnz >= 1 (A != 0,
  * Section 1).  stream: a hipStream_t (NULL = default stream).  On success *out owns host
  * metadata only; the workspace stays owned by the caller. */
