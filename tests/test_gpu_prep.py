@@ -63,12 +63,14 @@ def _case(name):
         return lpgen.make("zipf1m", 0.004), dict(precision=hprlp.FP64_A32)
     if name == "zipf_many_tiles":  # ~180k nonzeros: 44 sort tiles
         return lpgen.make("zipf1m", 0.016), {}
+    if name == "t1_zero":  # the dense inverse of A~A~^T built from either path's arrays
+        return lpgen.ot_lp(20, 30, seed=501), dict(t1_zero=1)
     return lpgen.make(name), {}
 
 
 CASES = ["tiny", "empty_row_and_col", "many_empty_columns", "single_row", "one_column",
          "long_rows_split", "no_ruiz_no_pc", "pc_only", "no_reorder", "transport",
-         "zipf_mixed", "zipf_a32", "zipf_many_tiles"]
+         "zipf_mixed", "zipf_a32", "zipf_many_tiles", "t1_zero"]
 
 
 def _pair(lp, iters, batched=False, lambdas=None, **opt):
@@ -101,7 +103,8 @@ def test_device_setup_bitwise(case):
     for k in ("dr", "dc", "x", "y", "z", "xcur", "ycur"):
         _same(d[k], h[k], (case, k))
     assert d["schedA"] == h["schedA"] and d["schedT"] == h["schedT"]
-    for k in ("iters", "restarts", "power_iters", "lambda", "sigma", "pobj", "rel_p", "rel_d"):
+    for k in ("iters", "restarts", "power_iters", "lambda", "sigma", "pobj", "rel_p", "rel_d",
+              "beta_b", "beta_c"):
         _same(np.float64(d["stats"][k]), np.float64(h["stats"][k]), (case, k))
     print(case, lp.m, lp.n, lp.nnz, "prep ms host/device",
           round(h["stats"]["t_prep_ms"], 2), round(d["stats"]["t_prep_ms"], 2))
