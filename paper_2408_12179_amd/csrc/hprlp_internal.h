@@ -215,7 +215,7 @@ hipError_t prep_vectors(const PrepArgs &a, const int *row_off, const int *col_of
 // ---------------------------------------------------------------- T1 = 0 (t1zero.hip)
 // Section 3.2, item 1: LPs without inequality rows, y-step solved exactly through the
 // dense inverse G of A~A~^T (at most kT1MaxRows rows).
-constexpr int kT1MaxRows = 4096;
+constexpr int kT1MaxRows = 8192;  // k_gram / k_linv hold m doubles (64 KB) in LDS
 size_t t1_parts_len();
 // G = (A~A~^T)^{-1} via LDL^T; F, LT: m*m scratch; diag0 / diagd: the diagonal of A~A~^T
 // and the LDL^T pivots (for the rank check on the host)

@@ -267,9 +267,9 @@ def test_t1_zero_limits(lib):
         hprlp.workspace_bytes(100, 5, 400, 2000, o)  # inequality rows
     assert e.value.code == hprlp.EINVAL
     with pytest.raises(hprlp.HPRLPError) as e:
-        hprlp.workspace_bytes(4097, 0, 40000, 200000, o)  # beyond the dense inverse
+        hprlp.workspace_bytes(8193, 0, 40000, 200000, o)  # beyond the dense inverse
     assert e.value.code == hprlp.EDIM
-    assert hprlp.workspace_bytes(4096, 0, 40000, 200000, o) >= 3 * 8 * 4096 * 4096
+    assert hprlp.workspace_bytes(8192, 0, 40000, 200000, o) >= 3 * 8 * 8192 * 8192
     with pytest.raises(hprlp.HPRLPError) as e:
         hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=1,
                                                                        precision=hprlp.MIXED))

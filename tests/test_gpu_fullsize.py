@@ -120,3 +120,21 @@ def test_fullsize_ot4m_t1zero_first_y_step():
     assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs), \
         np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs)
     s.close()
+
+
+def test_t1zero_at_the_row_limit():
+    """T1 = 0 near its row limit (OT 4096 x 4096: m = 8191, n = 16.8M): eq. AATy=R holds for
+    the first y-step, as in the ot4m test."""
+    import scipy.sparse as sp
+    lp = lpgen.ot_lp(4096, 4096, seed=11)
+    s = hprlp.Solver(lp, t1_zero=1, max_iter=1)
+    sol = s.solve()
+    dr, dc = s.iterate(hprlp.DROW), s.iterate(hprlp.DCOL)
+    bb, bc = sol.stats["beta_b"], sol.stats["beta_c"]
+    A = sp.csr_matrix((lp.val, lp.colidx, lp.rowptr), shape=(lp.m, lp.n))
+    At = sp.diags(dr) @ A @ sp.diags(dc)
+    xb, yb = sol.x / (bb * dc), sol.y / (bc * dr)
+    lhs = At @ (At.T @ yb)
+    rhs = dr * lp.b / bb - 2.0 * (At @ xb)
+    assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs)
+    s.close()
