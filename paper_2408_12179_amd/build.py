@@ -10,6 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build", "hprlp")
 LIB = os.path.join(PKG, "libhprlp.so")
+EXAMPLE = os.path.join(PKG, "examples", "solve_transport")
 SOURCES = ["kernels.hip", "prep.hip", "t1zero.hip", "setup.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -37,6 +38,13 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)
+    # the C example: plain C against the C ABI and the HIP runtime API only
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__",
+                    "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+                    EXAMPLE + ".c", "-L", PKG, "-lhprlp", "-L", os.path.join(rocm, "lib"),
+                    "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN/..",
+                    "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", EXAMPLE], check=True)
     if verbose:
         print("built", LIB)
     return LIB
