@@ -20,8 +20,9 @@ U{5..40}; Zipf(1.1) column popularity; plain FP64).  --config selects the other 
   ot4m          balanced optimal transport 2048 x 2048 (m = 4095 equality rows, n = 4.19M),
                 FP64; with --t1-zero the T1 = 0 variant of Section 3.2 (exact y-step)
 --compare adds the plain-FP64 GPU solver on the same instances under the same time budget:
-the FP64 single-LP solve for the mixed-precision workloads, and for batch256 the single-LP
-FP64 solver run on the instances one after another.
+the FP64 single-LP solve for the mixed-precision workloads (with --t1-zero: the default
+variant T1 = lambda I - A A^T), and for batch256 the single-LP FP64 solver run on the
+instances one after another.
 --ablation instead runs the four steps of the paper's ablation (Section 4.2, Fig. 1: DR;
 + restart and Halpern; + sigma update; + relaxation rho = 2, i.e. HPR-LP) on the first 64
 batch256 instances, each variant as one batched solve capped at --time-limit, and prints one
@@ -347,7 +348,11 @@ def main():
                 "instance_iters_per_s": it_sum / max(t_used, 1e-9),
                 "note": "same time budget, solves only (creates excluded)"}
         else:
-            print("[bench] compare: plain FP64 solve of the same LP", file=sys.stderr, flush=True)
+            if args.t1_zero:  # the reference point is the default variant, T1 = lambda I - A A^T
+                fp64["t1_zero"] = 0
+            print("[bench] compare: plain FP64 solve of the same LP"
+                  + (" with T1 = lambda I - A A^T" if args.t1_zero else ""),
+                  file=sys.stderr, flush=True)
             s64 = hprlp.Solver(lp, **fp64)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
