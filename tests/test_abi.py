@@ -279,3 +279,22 @@ def test_t1_zero_limits(lib):
     assert e.value.code == hprlp.EINVAL
     with pytest.raises(hprlp.HPRLPError):
         hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=2))
+
+
+def test_create_rejects_a_workspace_sized_for_host_preprocessing(lib):
+    # the default (device) preprocessing needs its scratch inside the workspace: a workspace
+    # sized with setup_on_host = 1 is rejected before any HIP call, naming the size it needs
+    lp = lpgen.make("tiny")
+    small = hprlp.workspace_bytes(lp.m1, lp.m2, lp.n, lp.nnz,
+                                  hprlp.default_options(setup_on_host=1))
+    need = hprlp.workspace_bytes(lp.m1, lp.m2, lp.n, lp.nnz, hprlp.default_options())
+    assert small < need
+    o = hprlp.default_options()
+    arrs = [np.ascontiguousarray(lp.rowptr, dtype=np.int64),
+            np.ascontiguousarray(lp.colidx, dtype=np.int32)] + \
+        [np.ascontiguousarray(a, dtype=np.float64) for a in (lp.val, lp.b, lp.c, lp.l, lp.u)]
+    h = C.c_void_p()
+    rc = lib.hprlp_create(C.byref(h), lp.m1, lp.m2, lp.n, *[C.c_void_p(a.ctypes.data) for a in arrs],
+                          C.byref(o), C.c_void_p(256), small, None)
+    msg = lib.hprlp_last_error(None).decode()
+    assert rc == hprlp.EINVAL and "workspace too small" in msg and str(need) in msg, msg
