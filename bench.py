@@ -146,9 +146,22 @@ def ablation(args):
         print(f"[bench] ablation {name}: {sum(solved)}/{len(per)} solved, SGM10 iterations "
               f"{sgm:.0f}, {wall:.1f} s", file=sys.stderr, flush=True)
         s.close()
+    # the same steps on the tiny LP, solved alone: iterations to the tolerance
+    tiny = lpgen.make("tiny")
+    tiny_rows = []
+    for name, kw in ABLATION:
+        s = hprlp.Solver(tiny, tol=args.tol, max_iter=200_000, **kw)
+        sol = s.solve()
+        tiny_rows.append({"variant": name, "status": sol.status,
+                          "iters": int(sol.stats["iters"]),
+                          "solve_ms": sol.stats["t_solve_ms"]})
+        print(f"[bench] ablation tiny {name}: {sol.status} in {sol.stats['iters']} iterations",
+              file=sys.stderr, flush=True)
+        s.close()
     print(json.dumps({"ablation": rows, "workload": "first 64 batch256 instances",
                       "tol": args.tol, "time_limit_s": args.time_limit,
-                      "note": "unsolved instances count with the iterations run"}), flush=True)
+                      "note": "unsolved instances count with the iterations run",
+                      "ablation_tiny": tiny_rows}), flush=True)
 
 
 def main():
