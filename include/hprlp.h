@@ -99,7 +99,8 @@ typedef struct {
                              /* inside the library (denser gather cache lines); results    */
                              /* are returned in the caller's order either way              */
     int profile;             /* N > 0: time the passes of every N-th iteration with HIP    */
-                             /* events (stats col/row_pass_ms); 0: off                     */
+                             /* events (stats col/row_pass_ms and _launches); a batched     */
+                             /* solve places the events as nodes of its chunk graphs; 0: off */
     int verbose;             /* 1: one log line per check on stderr                        */
     int autotune;            /* 1: at create, time candidate schedules of A and A^T on the  */
                              /* uploaded problem and keep the fastest per matrix (problems  */
@@ -234,12 +235,28 @@ int hprlp_create_batched(hprlp_handle **out, int32_t n_inst, const int64_t *inst
  * *status is OPTIMAL only if every instance is, else the first other status met. */
 int hprlp_solve(hprlp_handle *h, double *x, double *y, double *z, int *status);
 
-/* Run `iters` more iterations of Algorithm 2 (the column and row passes, Section 3.3) from
- * the current state of a single-LP handle, continuing the current outer loop (t and k
- * advance) with no check, restart or sigma update: a debugging / parity aid that exposes the
- * plain fixed-point map.  Needs a previous hprlp_solve on the handle (ESTATE otherwise);
- * EINVAL on a batched handle or iters < 0.  The returned w_bar (XBAR, YBAR, ZBAR) stays that
- * of the last check; XCUR / YCUR give the new current iterate.  Blocks until done. */
+/* Start a solve without iterating: lambda by the power method unless given (Section 4.1,
+ * "Initialization and parameter setting"), sigma = sigma0 and the origin w = 0 with
+ * t = k = r = 0 (every instance of a batched handle).  The iterations then advance with
+ * hprlp_step; hprlp_stats reports power_iters, lambda and t_power_ms.  If the power method
+ * gives lambda <= 0, the stats report HPRLP_NUMERICAL and hprlp_step returns ESTATE.  Blocks
+ * until done. */
+int hprlp_begin(hprlp_handle *h);
+
+/* Advance the solve of Algorithm 2 from the current state (left by hprlp_begin or a solve).
+ * Single-LP handle: `iters` more iterations (the column and row passes, Section 3.3),
+ *   continuing the current outer loop (t and k advance) with no check, restart or sigma
+ *   update: a debugging / parity aid that exposes the plain fixed-point map.  The returned
+ *   w_bar (XBAR, YBAR, ZBAR) stays that of the last check; XCUR / YCUR give the new current
+ *   iterate.
+ * Batched handle: `iters` must be a multiple of check_every; runs iters / check_every whole
+ *   chunks exactly as hprlp_solve runs them (each with its checks, the restart, sigma and
+ *   termination decisions of every instance, Sections 3.1, 3.2 and 4.1), stopping early once
+ *   every instance has stopped or max_iter / time_limit (counted from hprlp_begin) is hit,
+ *   after which further steps run nothing; hprlp_stats / hprlp_stats_instance and the XBAR,
+ *   YBAR, ZBAR iterates then describe the batch as it stands.
+ * ESTATE before hprlp_begin or a solve; EINVAL on iters < 0 (or not a multiple of
+ * check_every for a batch).  Blocks until done. */
 int hprlp_step(hprlp_handle *h, int iters);
 
 /* Statistics of the last solve.  Batched handle: iters = iterations run, restarts summed,
@@ -249,7 +266,9 @@ int hprlp_stats(const hprlp_handle *h, hprlp_stats_t *out);
 
 /* Statistics of instance i (0 <= i < n_inst; a single-LP handle has instance 0 only) of
  * the last solve: its own iters (iterations until it stopped), restarts, sigma, lambda,
- * residuals, objectives, beta_b, beta_c, n_checks and status.  ESTATE before a solve. */
+ * residuals, objectives, beta_b, beta_c, n_checks and status.  Batched: t_solve_ms is the
+ * time from the start of the solve to the end of the chunk whose check stopped the instance
+ * (the time so far while it still iterates).  ESTATE before a solve. */
 int hprlp_stats_instance(const hprlp_handle *h, int32_t i, hprlp_stats_t *out);
 
 /* Copy one iterate (hprlp_iterate) of the last solve into out (host or device pointer,

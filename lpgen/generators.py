@@ -231,6 +231,31 @@ def bernoulli_lp(m1: int, m2: int, n: int, density: float, seed: int, name="bern
               meta=dict(family="bernoulli", density=density, seed=seed))
 
 
+def mixed_bounds_lp(m1: int, m2: int, n: int, density: float, seed: int,
+                    name="mixed_bounds") -> LP:
+    """Bernoulli LP whose columns take every kind of bound, in equal shares: boxed
+    [l, u] (l ~ U(-5, 0), u = l + U(1, 10)), fixed l = u ~ U(-3, 3), lower-only [l, +inf),
+    upper-only (-inf, u] and free.  Certificate as for bernoulli_lp (a fixed column is a box
+    of width 0: x0 = l = u with any sign of z0)."""
+    rng = np.random.default_rng(seed)
+    m = m1 + m2
+    lengths = rng.binomial(n, density, size=m).astype(np.int64)
+    rowptr = _rows_from_lengths(lengths)
+    nnz = int(rowptr[-1])
+    col = rng.integers(0, n, size=nnz).astype(np.int64)
+    col = _dedupe_rows(rowptr, col, lambda k: rng.integers(0, n, size=k), n)
+    val = _fp32_normal(rng, nnz)
+    kind = rng.integers(0, 5, size=n)
+    lo = rng.uniform(-5.0, 0.0, n)
+    width = rng.uniform(1.0, 10.0, n)
+    fix = rng.uniform(-3.0, 3.0, n)
+    l = np.select([kind == 0, kind == 1, kind == 2], [lo, fix, lo], -np.inf)
+    u = np.select([kind == 0, kind == 1, kind == 3], [lo + width, fix, lo + width], np.inf)
+    b, c, cert = _certificate(rng, rowptr, col, val, m1, m2, n, l, u)
+    return LP(name, m1, m2, n, rowptr, col.astype(np.int32), val, b, c, l, u, cert,
+              meta=dict(family="mixed_bounds", density=density, seed=seed))
+
+
 def zipf_lp(m1: int, m2: int, n: int, seed: int, row_len=(5, 40), zipf_s=1.1,
             free_frac=0.3, ub_range=(1.0, 100.0), name="zipf") -> LP:
     """Large sparse LP: row lengths U{row_len}, columns drawn from a bounded Zipf(zipf_s)

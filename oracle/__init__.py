@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hprlp_oracle.c")
 LIB = os.path.join(HERE, "libhprlp_oracle.so")
+LIB_OMP = os.path.join(HERE, "libhprlp_oracle_omp.so")  # same source, -fopenmp (timing only)
 
 # check-trace columns (one row per check), same order as the C enum
 TRACE_COLS = ["k", "t", "r", "sigma", "merit", "merit0", "merit_prev", "rel_p", "rel_d",
@@ -54,25 +55,30 @@ DEFAULTS = dict(tol=1e-8, check_every=150, max_iter=1_000_000, time_limit=0.0, a
                 t1_zero=0)
 
 
+_FLAGS = ["-O2", "-std=c11", "-D_POSIX_C_SOURCE=199309L", "-ffp-contract=off",
+          "-fno-fast-math", "-fPIC", "-shared"]
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FP contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_POSIX_C_SOURCE=199309L",
-                               "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FP contraction), and the same
+    source with -fopenmp (bit-identical results on several threads; for timing)."""
+    for lib, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["gcc", *_FLAGS, *extra, SRC, "-o", tmp, "-lm"])
+            os.replace(tmp, lib)
     return LIB
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
+def _load(threads: int = 1):
+    """The plain build (threads = 1) or the OpenMP build set to `threads` threads."""
+    key = "plain" if threads == 1 else "omp"
+    if key not in _libs:
         build()
-        lib = C.CDLL(LIB)
+        lib = C.CDLL(LIB if key == "plain" else LIB_OMP)
         P = C.c_void_p
         lib.oracle_scale.argtypes = [C.c_longlong, C.c_longlong, P, P, P, P, P, P, P,
                                      C.POINTER(Opts), P, P, P, P, P, P, P,
@@ -85,8 +91,13 @@ def _load():
                                      P, P, C.POINTER(Opts), P, P, P, P, P, C.POINTER(Result),
                                      P, C.c_longlong, P, C.c_longlong, P]
         lib.oracle_solve.restype = C.c_int
-        _lib = lib
-    return _lib
+        lib.oracle_set_threads.argtypes = [C.c_int]
+        lib.oracle_set_threads.restype = C.c_int
+        _libs[key] = lib
+    lib = _libs[key]
+    if key == "omp":
+        lib.oracle_set_threads(int(threads))
+    return lib
 
 
 def _p(a: Optional[np.ndarray]):
@@ -187,9 +198,11 @@ class SolveResult:
         return self.trace[:, TRACE_COLS.index(name)]
 
 
-def solve(lp, check_cap: int = 100000, iter_cap: int = 0, **kw) -> SolveResult:
-    """Run HPR-LP (Algorithm 2) on the CPU.  Keyword options as in ``DEFAULTS``."""
-    lib = _load()
+def solve(lp, check_cap: int = 100000, iter_cap: int = 0, threads: int = 1,
+          **kw) -> SolveResult:
+    """Run HPR-LP (Algorithm 2) on the CPU.  Keyword options as in ``DEFAULTS``.
+    threads > 1 runs the OpenMP build (same results bit for bit; for timing)."""
+    lib = _load(threads)
     rp, ci, val = _csr(lp)
     m, n = lp.m, lp.n
     o = _opts(**kw)

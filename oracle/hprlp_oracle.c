@@ -43,13 +43,20 @@
  *     the termination test uses the original data.
  *   - delta*_C(-z) = sum_j ( max(-z_j,0) u_j - max(z_j,0) l_j ) with 0 * inf := 0.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math).
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math).  This plain
+ * single-thread build is the pinned oracle.  The same source built with -fopenmp runs the
+ * products and the per-element loops of an iteration on several threads, with every sum in
+ * the same order (reductions stay serial), so its results are bit-identical; it exists only
+ * to time the oracle on all host cores.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     double tol;            /* termination tolerance epsilon                         */
@@ -97,22 +104,79 @@ static double now_s(void) {
     return ts.tv_sec + 1e-9 * ts.tv_nsec;
 }
 
-/* out = M x for a CSR matrix M (rows m). */
-static void csr_mv(long long m, const int64_t *rp, const int32_t *ci, const double *v,
-                   const double *x, double *out) {
-    for (long long i = 0; i < m; ++i) {
+/* A CSR matrix M (m rows, n columns).  The OpenMP build (compiled with -fopenmp, used only
+ * to time the oracle on all host cores) also stores M^T, with the entries of each column in
+ * increasing row order, so that M^T y is a per-column gather whose sums run in the same
+ * order as the row-by-row scatter of the plain build: both builds give identical bits. */
+typedef struct {
+    long long m, n;
+    const int64_t *rp; const int32_t *ci; const double *v;
+    int64_t *tp; int32_t *tr; double *tv;   /* transpose (OpenMP build), else NULL */
+} csr_t;
+
+static int csr_init(csr_t *M, long long m, long long n, const int64_t *rp, const int32_t *ci,
+                    const double *v) {
+    M->m = m; M->n = n; M->rp = rp; M->ci = ci; M->v = v;
+    M->tp = NULL; M->tr = NULL; M->tv = NULL;
+#ifdef _OPENMP
+    long long nnz = rp[m];
+    M->tp = calloc(n + 1, sizeof(int64_t));
+    M->tr = malloc(sizeof(int32_t) * (nnz ? nnz : 1));
+    M->tv = malloc(sizeof(double) * (nnz ? nnz : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (n ? n : 1));
+    if (!M->tp || !M->tr || !M->tv || !fill) { free(fill); return -6; }
+    for (int64_t p = 0; p < nnz; ++p) M->tp[ci[p] + 1]++;
+    for (long long j = 0; j < n; ++j) M->tp[j + 1] += M->tp[j];
+    for (long long j = 0; j < n; ++j) fill[j] = M->tp[j];
+    for (long long i = 0; i < m; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            int64_t q = fill[ci[p]]++;
+            M->tr[q] = (int32_t)i;
+            M->tv[q] = v[p];
+        }
+    free(fill);
+#endif
+    return 0;
+}
+
+static void csr_free(csr_t *M) { free(M->tp); free(M->tr); free(M->tv); }
+
+/* out = M x */
+static void csr_mv(const csr_t *M, const double *x, double *out) {
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < M->m; ++i) {
         double s = 0.0;
-        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += v[p] * x[ci[p]];
+        for (int64_t p = M->rp[i]; p < M->rp[i + 1]; ++p) s += M->v[p] * x[M->ci[p]];
         out[i] = s;
     }
 }
 
-/* out = M^T y for a CSR matrix M (rows m, columns n), by scattering row by row. */
-static void csr_mtv(long long m, long long n, const int64_t *rp, const int32_t *ci,
-                    const double *v, const double *y, double *out) {
-    for (long long j = 0; j < n; ++j) out[j] = 0.0;
-    for (long long i = 0; i < m; ++i)
-        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) out[ci[p]] += v[p] * y[i];
+/* out = M^T y: row by row, scattering (the plain build); per column over the stored
+ * transpose, in the same order (the OpenMP build). */
+static void csr_mtv(const csr_t *M, const double *y, double *out) {
+    if (M->tp) {
+#pragma omp parallel for schedule(static)
+        for (long long j = 0; j < M->n; ++j) {
+            double s = 0.0;
+            for (int64_t q = M->tp[j]; q < M->tp[j + 1]; ++q) s += M->tv[q] * y[M->tr[q]];
+            out[j] = s;
+        }
+        return;
+    }
+    for (long long j = 0; j < M->n; ++j) out[j] = 0.0;
+    for (long long i = 0; i < M->m; ++i)
+        for (int64_t p = M->rp[i]; p < M->rp[i + 1]; ++p) out[M->ci[p]] += M->v[p] * y[i];
+}
+
+/* Number of threads of the OpenMP build (1 in the plain build). */
+int oracle_set_threads(int k) {
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+    return omp_get_max_threads();
+#else
+    (void)k;
+    return 1;
+#endif
 }
 
 static double dot(long long k, const double *a, const double *b) {
@@ -202,14 +266,17 @@ int oracle_power(long long m, long long n, const int64_t *rp, const int32_t *ci,
                  const double *val, int max_iter, double tol, double *lambda) {
     double *v = malloc(sizeof(double) * m), *w = malloc(sizeof(double) * n);
     double *s = malloc(sizeof(double) * m);
-    if (!v || !w || !s) { free(v); free(w); free(s); return -6; }
+    csr_t M;
+    if (!v || !w || !s || csr_init(&M, m, n, rp, ci, val)) {
+        free(v); free(w); free(s); return -6;
+    }
     for (long long i = 0; i < m; ++i) v[i] = 1.0 / sqrt((double)m);
     double rq = 0.0, rq_prev = 0.0;
     int it = 0;
     for (it = 1; it <= max_iter; ++it) {
-        csr_mtv(m, n, rp, ci, val, v, w); /* w = A^T v           */
+        csr_mtv(&M, v, w);                /* w = A^T v           */
         rq = dot(n, w, w);                /* v^T A A^T v, ||v||=1 */
-        csr_mv(m, rp, ci, val, w, s);     /* s = A A^T v          */
+        csr_mv(&M, w, s);                 /* s = A A^T v          */
         double ns = nrm2(m, s);
         if (ns == 0.0) break;
         for (long long i = 0; i < m; ++i) v[i] = s[i] / ns;
@@ -219,6 +286,7 @@ int oracle_power(long long m, long long n, const int64_t *rp, const int32_t *ci,
     if (it > max_iter) it = max_iter;
     *lambda = rq;
     free(v); free(w); free(s);
+    csr_free(&M);
     return it;
 }
 
@@ -237,6 +305,7 @@ typedef struct {
     long long m1, m, n;
     const int64_t *rp; const int32_t *ci;
     const double *val;     /* original A */
+    csr_t Ao;              /* original A as a product operand */
     const double *b, *c, *l, *u;
     const double *val_s;   /* scaled A~ */
     const double *dr, *dc, *b_s, *c_s, *l_s, *u_s;
@@ -254,10 +323,10 @@ static void original_residuals(const problem *P, const double *xb, const double 
         zo[j] = P->beta_c * zb[j] / P->dc[j];
     }
     for (long long i = 0; i < m; ++i) yo[i] = P->beta_c * P->dr[i] * yb[i];
-    csr_mv(m, P->rp, P->ci, P->val, xo, work_m); /* A x */
+    csr_mv(&P->Ao, xo, work_m); /* A x */
     for (long long i = 0; i < m; ++i) work_m[i] = P->b[i] - work_m[i];
     double np = sqrt(proj_D_sq(P->m1, m, work_m));
-    csr_mtv(m, n, P->rp, P->ci, P->val, yo, work_n); /* A^T y */
+    csr_mtv(&P->Ao, yo, work_n); /* A^T y */
     for (long long j = 0; j < n; ++j) work_n[j] = P->c[j] - work_n[j] - zo[j];
     double nd = nrm2(n, work_n);
     double bnorm = nrm2(m, P->b), cnorm = nrm2(n, P->c);
@@ -362,6 +431,8 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
 
     oracle_scale(m, n, rp, ci, val, b, c, l, u, o, val_s, dr, dc, b_s, c_s, l_s, u_s,
                  &P.beta_b, &P.beta_c);
+    csr_t As; /* the scaled matrix A~ */
+    if (csr_init(&As, m, n, rp, ci, val_s) || csr_init(&P.Ao, m, n, rp, ci, val)) return -6;
     P.val_s = val_s; P.dr = dr; P.dc = dc; P.b_s = b_s; P.c_s = c_s; P.l_s = l_s;
     P.u_s = u_s;
     if (scaling_out) {
@@ -405,7 +476,8 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
     for (;;) {
         /* ---- one iteration of Algorithm 2 ---- */
         /* z-step and x-step (eqs. update-z, update-x): v = x + sigma (A^T y - c) */
-        csr_mtv(m, n, rp, ci, val_s, y, g);
+        csr_mtv(&As, y, g);
+#pragma omp parallel for schedule(static)
         for (long long j = 0; j < n; ++j) {
             v[j] = x[j] + sigma * (g[j] - c_s[j]);
             xb[j] = clampd(v[j], l_s[j], u_s[j]);
@@ -413,12 +485,13 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
             xr[j] = 2.0 * xb[j] - x[j];
         }
         /* y-step (eq. update-y-2) with T1 = lambda I - A A^T */
-        csr_mv(m, rp, ci, val_s, xr, s);
+        csr_mv(&As, xr, s);
         if (o->t1_zero) {  /* T1 = 0: exact minimiser (eq. AATy=R), no inequality rows */
             for (long long i = 0; i < m; ++i) wm[i] = b_s[i] - s[i];
             chol_solve(m, Lc, wm);
             for (long long i = 0; i < m; ++i) yb[i] = y[i] + wm[i] / sigma;
         } else {
+#pragma omp parallel for schedule(static)
             for (long long i = 0; i < m; ++i) {
                 double yi = y[i] + (b_s[i] - s[i]) / (lambda * sigma);
                 if (i >= m1 && yi < 0.0) yi = 0.0;
@@ -426,11 +499,13 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
             }
         }
         /* reflection w_hat = rho w_bar + (1 - rho) w, and d = w - w_hat for the merit */
+#pragma omp parallel for schedule(static)
         for (long long j = 0; j < n; ++j) {
             double xh = o->rho * xb[j] + (1.0 - o->rho) * x[j];
             dx[j] = x[j] - xh;
             wn[j] = xh;
         }
+#pragma omp parallel for schedule(static)
         for (long long i = 0; i < m; ++i) {
             double yh = o->rho * yb[i] + (1.0 - o->rho) * y[i];
             dy[i] = y[i] - yh;
@@ -448,10 +523,10 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
         if (first || want_check || o->trace_every_iter) {
             /* R~ = ||w - w_hat||_M, M of eq. def:M with T1 = lambda I - A A^T:
              * ||d||_M^2 = sigma lambda ||dy||^2 + 2 <dy, A dx> + ||dx||^2 / sigma */
-            csr_mv(m, rp, ci, val_s, dx, s);
+            csr_mv(&As, dx, s);
             double ty;  /* <dy, (T1 + A A^T) dy> */
             if (o->t1_zero) {
-                csr_mtv(m, n, rp, ci, val_s, dy, gt);
+                csr_mtv(&As, dy, gt);
                 ty = dot(n, gt, gt);
             } else {
                 ty = lambda * dot(m, dy, dy);
@@ -462,7 +537,7 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
         if (o->trace_every_iter && iter_trace && nit < iter_cap) {
             /* KKT residual map R(w_bar) on the scaled problem (Section 2, eq. def:KKT_residual) */
             double acc = 0.0, viol_x = 0.0, viol_y = 0.0;
-            csr_mv(m, rp, ci, val_s, xb, s);
+            csr_mv(&As, xb, s);
             for (long long i = 0; i < m; ++i) {
                 double arg = yb[i] - s[i] + b_s[i];
                 double pr = (i >= m1 && arg < 0.0) ? 0.0 : arg;
@@ -477,7 +552,7 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
                 if (vl > viol_x) viol_x = vl;
                 if (vu > viol_x) viol_x = vu;
             }
-            csr_mtv(m, n, rp, ci, val_s, yb, g);
+            csr_mtv(&As, yb, g);
             for (long long j = 0; j < n; ++j) {
                 double e = c_s[j] - g[j] - zb[j];
                 acc += e * e;
@@ -493,8 +568,10 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
         /* Halpern step (Algorithm 2): w = w0/(t+2) + (t+1)/(t+2) w_hat, with t the inner
          * counter before the increment above */
         double tb = (double)(t - 1);
+#pragma omp parallel for schedule(static)
         for (long long j = 0; j < n; ++j)
             x[j] = o->use_halpern ? x0[j] / (tb + 2.0) + ((tb + 1.0) / (tb + 2.0)) * wn[j] : wn[j];
+#pragma omp parallel for schedule(static)
         for (long long i = 0; i < m; ++i)
             y[i] = o->use_halpern ? y0[i] / (tb + 2.0) + ((tb + 1.0) / (tb + 2.0)) * wm[i] : wm[i];
 
@@ -545,15 +622,15 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
             for (long long i = 0; i < m; ++i) wm[i] = yb[i] - y0[i];
             Dx = nrm2(n, wn);
             if (o->t1_zero) {  /* eq. sigma_T1=0 */
-                csr_mtv(m, n, rp, ci, val_s, wm, gt);
+                csr_mtv(&As, wm, gt);
                 Dy = nrm2(n, gt);
             } else {
                 Dy = sqrt(lambda) * nrm2(m, wm);
             }
-            csr_mv(m, rp, ci, val_s, xb, s);
+            csr_mv(&As, xb, s);
             for (long long i = 0; i < m; ++i) wm[i] = b_s[i] - s[i];
             err_p = sqrt(proj_D_sq(m1, m, wm)) / (1.0 + bs_norm);
-            csr_mtv(m, n, rp, ci, val_s, yb, g);
+            csr_mtv(&As, yb, g);
             for (long long j = 0; j < n; ++j) wn[j] = c_s[j] - g[j] - zb[j];
             err_d = nrm2(n, wn) / (1.0 + cs_norm);
             int ok = Dx > 1e-16 && Dx < 1e12 && Dy > 1e-16 && Dy < 1e12 && err_p > 0.0 &&
@@ -592,5 +669,6 @@ int oracle_solve(long long m1, long long m2, long long n, const int64_t *rp,
     free(x); free(y); free(x0); free(y0); free(xb); free(yb); free(zb); free(v); free(g);
     free(s); free(xr); free(dx); free(dy); free(wm); free(wn); free(xo); free(yo); free(zo);
     free(Lc); free(gt);
+    csr_free(&As); csr_free(&P.Ao);
     return 0;
 }

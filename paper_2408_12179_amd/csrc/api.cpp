@@ -88,6 +88,20 @@ struct BatchDev {
     int *segA_ptr = nullptr, *segA_slots = nullptr, *segT_ptr = nullptr, *segT_slots = nullptr;
 };
 
+// State of a batched run between hprlp_begin / hprlp_solve and the chunks that follow.
+struct BatchRun {
+    bool begun = false, done = false;
+    double t_start = 0.0, t_power = 0.0;     // host clock (ms) at the start; power method
+    int piters = 0;
+    long long k = 0, iters_fp32 = 0;         // iterations of the batch; of its FP32 phase
+    double prev_active = 0.0;
+    int st_all = 0;                          // status of instances still iterating at the end
+    std::vector<double> kkt_hist, lam;
+    std::vector<std::pair<long long, double>> chunk_end;  // (k, ms since t_start) per chunk
+    double prof_ms[2] = {0.0, 0.0};          // profile: summed column / row pass times
+    long long prof_n[2] = {0, 0};
+};
+
 }  // namespace
 
 struct hprlp_handle {
@@ -122,6 +136,8 @@ struct hprlp_handle {
     std::vector<double> lam_given;          // per-instance lambda from the caller (or empty)
     hipGraphExec_t graphs[3] = {nullptr, nullptr, nullptr};
     std::vector<hprlp_stats_t> inst_stats;
+    BatchRun br;                               // state of the batched run in progress
+    bool no_graph_events = false;              // profile: event nodes could not be captured
     // schedule parameters of A and A^T (the autotuner may pick different ones per matrix)
     ScheduleParams spA{}, spT{};
     double tuned_ms[2] = {0.0, 0.0};          // autotuner: best row / column pass time
@@ -1585,10 +1601,10 @@ int run_plain(hprlp_handle *h, long long count) {
     return HPRLP_OK;
 }
 
-int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) {
+// Start of a single-LP solve: lambda (power method unless given; Section 4.1), sigma0 and
+// the origin, with t = k = r = 0.  Returns with h->lambda <= 0 reported as NUMERICAL.
+int single_begin(hprlp_handle *h, int *status, int *piters) {
     const hprlp_options &o = h->opt;
-    HIPCHK(h, hipStreamSynchronize(h->st));
-    const double t_start = now_ms();
     h->solved = false;  // outputs of an earlier solve are no longer the handle's
     h->trace.clear();
     h->stats = hprlp_stats_t{};
@@ -1596,23 +1612,33 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
     h->t = h->k = h->r = 0;
     h->sigma = o.sigma0;
     int rc;
-    int piters = 0;
+    *piters = 0;
     if (o.t1_zero) {
         h->lambda = 1.0;  // no lambda in this variant; 1 leaves the merit and Delta_y as above
     } else if (o.lambda_override > 0) {
         h->lambda = o.lambda_override;
     } else {
         std::vector<double> lam;
-        if ((rc = power_method(h, lam, &piters))) return rc;
+        if ((rc = power_method(h, lam, piters))) return rc;
         h->lambda = lam[0];
     }
-    const double t_power = now_ms() - t_start;
     if (!(h->lambda > 0.0) || !std::isfinite(h->lambda)) {
         h->stats.status = HPRLP_NUMERICAL;
         if (status) *status = HPRLP_NUMERICAL;
         return fail(h, HPRLP_OK, "power method gave lambda <= 0");
     }
-    if ((rc = zero_state(h))) return rc;
+    return zero_state(h);
+}
+
+int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) {
+    const hprlp_options &o = h->opt;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const double t_start = now_ms();
+    int rc;
+    int piters = 0;
+    if ((rc = single_begin(h, status, &piters))) return rc;
+    if (h->stats.status == HPRLP_NUMERICAL) return HPRLP_OK;
+    const double t_power = now_ms() - t_start;
 
     std::vector<ProfRec> prof;
     size_t ev_next = 0;
@@ -1821,20 +1847,46 @@ int set_schedules(hprlp_handle *h, const std::vector<int> &keep) {
     return HPRLP_OK;
 }
 
+// Event record during stream capture: an event node in the captured graph (its timestamp is
+// taken each time the graph runs); outside capture a plain record.
+hipError_t record_event(hipEvent_t ev, hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return e;
+    if (cs == hipStreamCaptureStatusActive) return hipEventRecordWithFlags(ev, st, hipEventRecordExternal);
+    return hipEventRecord(ev, st);
+}
+
+// Iterations of a chunk whose passes are bracketed by events (profile = N: every N-th).
+int profiled_iters(const hprlp_handle *h) {
+    const int L = (int)h->opt.check_every, N = h->opt.profile;
+    return (N > 0 && !h->no_graph_events) ? (L + N - 1) / N : 0;
+}
+
 // Record one chunk of check_every iterations on the library stream: first iteration (keep)
 // + its check sums, plain iterations, last iteration (keep) + check sums, the decisions of
-// every instance, the restart copies, and the iteration counter advance.
+// every instance, the restart copies, and the iteration counter advance.  With profile = N,
+// the passes of every N-th iteration are bracketed by events 3q, 3q+1 (after the column
+// pass) and 3q+2 (after the row pass) of the event pool.
 int record_chunk(hprlp_handle *h, int prec) {
     const int L = (int)h->opt.check_every;
+    const int N = profiled_iters(h) > 0 ? h->opt.profile : 0;
     const void *vs = prec == 1 ? static_cast<const void *>(&h->v32)
                                : static_cast<const void *>(&h->v64);
     const IterScalars unused{};  // batched passes read their scalars from device memory
+    for (int q = 0; q < 3 * profiled_iters(h); ++q)
+        if (!pool_event(h, (size_t)q)) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
     hipError_t e = hipSuccess;
     for (int i = 0; i < L && e == hipSuccess; ++i) {
         const bool keep = (i == 0 || i == L - 1);
+        const bool samp = N > 0 && i % N == 0;
+        const size_t e0 = samp ? (size_t)(3 * (i / N)) : 0;
         const BatchArgs ba = batch_args(h, i);
-        e = launch_col_pass(prec, keep, h->T, vs, unused, h->st, nullptr, &ba);
+        if (samp) e = record_event(h->ev_pool[e0], h->st);
+        if (e == hipSuccess) e = launch_col_pass(prec, keep, h->T, vs, unused, h->st, nullptr, &ba);
+        if (e == hipSuccess && samp) e = record_event(h->ev_pool[e0 + 1], h->st);
         if (e == hipSuccess) e = launch_row_pass(prec, keep, h->A, vs, unused, h->st, nullptr, &ba);
+        if (e == hipSuccess && samp) e = record_event(h->ev_pool[e0 + 2], h->st);
         if (e == hipSuccess && keep) {
             double *res = i == 0 ? h->bd.res_first : h->bd.res_chk;
             e = launch_check_row(prec, h->A, vs, h->chk, h->v64.bd, 0, h->partsA, res, h->st,
@@ -1872,9 +1924,14 @@ int get_graph(hprlp_handle *h, int prec, hipGraphExec_t *out) {
         const int rc = record_chunk(h, prec);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(h->st, &g);
-        if (rc) {
+        if (rc || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
-            return rc;
+            if (profiled_iters(h) > 0) {  // event nodes refused: capture without them
+                (void)hipGetLastError();
+                h->no_graph_events = true;
+                return get_graph(h, prec, out);
+            }
+            if (rc) return rc;
         }
         if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         hipGraphExec_t ex = nullptr;
@@ -1887,11 +1944,15 @@ int get_graph(hprlp_handle *h, int prec, hipGraphExec_t *out) {
     return HPRLP_OK;
 }
 
-int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status) {
+// Start of a batched solve: every instance at the origin with sigma = sigma0, k = 0, and
+// lambda per instance from the caller, lambda_override or the power method (Section 4.1).
+int batch_begin(hprlp_handle *h, int *status) {
     const hprlp_options &o = h->opt;
     const int ni = h->n_inst;
     if (h->user_st) HIPCHK(h, hipStreamSynchronize(h->user_st));
-    const double t_start = now_ms();
+    BatchRun &br = h->br;
+    br = BatchRun{};
+    br.t_start = now_ms();
     h->solved = false;  // outputs of an earlier solve are no longer the handle's
     h->stats = hprlp_stats_t{};
     h->inst_stats.clear();
@@ -1899,39 +1960,61 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
     h->n_compactions = 0;
     int rc;
     if (h->compacted && (rc = set_schedules(h, {}))) return rc;
-    // every instance iterates from w = 0 with sigma = sigma0; outer loops start at k = 0
     if ((rc = init_batch_state(h, o.sigma0, 0.0))) return rc;
-    std::vector<double> lam((size_t)ni, o.lambda_override);
-    int piters = 0;
-    if (!h->lam_given.empty()) lam = h->lam_given;
-    else if (!(o.lambda_override > 0) && (rc = power_method(h, lam, &piters))) return rc;
+    br.lam.assign((size_t)ni, o.lambda_override);
+    if (!h->lam_given.empty()) br.lam = h->lam_given;
+    else if (!(o.lambda_override > 0) && (rc = power_method(h, br.lam, &br.piters))) return rc;
     for (int b = 0; b < ni; ++b)
-        if (!(lam[b] > 0.0) || !std::isfinite(lam[b])) {
+        if (!(br.lam[b] > 0.0) || !std::isfinite(br.lam[b])) {
             h->stats.status = HPRLP_NUMERICAL;
             if (status) *status = HPRLP_NUMERICAL;
             return fail(h, HPRLP_OK, "power method gave lambda <= 0 for instance " + std::to_string(b));
         }
-    if ((rc = upload(h, h->bd.lam, lam.data(), lam.size()))) return rc;
-    const double t_power = now_ms() - t_start;
+    if ((rc = upload(h, h->bd.lam, br.lam.data(), br.lam.size()))) return rc;
+    br.t_power = now_ms() - br.t_start;
     if ((rc = zero_state(h))) return rc;
+    br.prev_active = (double)ni;
+    br.begun = true;
+    return HPRLP_OK;
+}
 
-    std::vector<double> kkt_hist;
-    long long k = 0, iters_fp32 = 0;
-    double prev_active = (double)ni;
-    int st_all = HPRLP_UNSOLVED;
-    for (;;) {
+// Run up to max_chunks chunks (< 0: until every instance has stopped or a limit of the
+// options is hit).  Each chunk is one launch of the captured graph and one 32-byte
+// read-back of the summary; stopped instances are dropped from the schedules as they
+// accumulate, and a MIXED batch switches to FP64 per reading 22 of the design.
+int batch_run(hprlp_handle *h, long long max_chunks) {
+    const hprlp_options &o = h->opt;
+    const int ni = h->n_inst;
+    BatchRun &br = h->br;
+    int rc;
+    for (long long c = 0; (max_chunks < 0 || c < max_chunks) && !br.done; ++c) {
         hipGraphExec_t ex;
         if ((rc = get_graph(h, h->prec, &ex))) return rc;
         HIPCHK(h, hipGraphLaunch(ex, h->st));
         if ((rc = download(h, h->pinned, h->bd.summary, 4))) return rc;
+        const double t_chunk = now_ms() - br.t_start;
         const double n_active = h->pinned[0], max_kkt = h->pinned[1], n_above = h->pinned[2];
-        k = (long long)h->pinned[3];
-        if (h->prec == 1) iters_fp32 = k;
+        br.k = (long long)h->pinned[3];
+        br.chunk_end.push_back({br.k, t_chunk});
+        if (h->prec == 1) br.iters_fp32 = br.k;
+        for (int q = 0; q < profiled_iters(h); ++q) {  // the graph's event nodes of this chunk
+            float a = 0.f, b2 = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&a, h->ev_pool[3 * q], h->ev_pool[3 * q + 1]));
+            HIPCHK(h, hipEventElapsedTime(&b2, h->ev_pool[3 * q + 1], h->ev_pool[3 * q + 2]));
+            br.prof_ms[0] += a;
+            br.prof_ms[1] += b2;
+            br.prof_n[0] += 1;
+            br.prof_n[1] += 1;
+        }
         if (o.verbose)
             std::fprintf(stderr, "hprlp batch k=%lld active=%.0f max_kkt=%.2e scheduled_nnz=%lld\n",
-                         k, n_active, max_kkt, (long long)h->sched_nnz);
-        if (n_active == 0) break;
-        if (n_active < prev_active) {
+                         br.k, n_active, max_kkt, (long long)h->sched_nnz);
+        if (n_active == 0) {
+            br.prev_active = 0.0;
+            br.done = true;
+            break;
+        }
+        if (n_active < br.prev_active) {
             // drop the stopped instances from the schedules once they hold an eighth of the
             // scheduled nonzeros (their work items still stream their nonzeros; only the
             // writes are skipped)
@@ -1944,62 +2027,78 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
                 if ((rc = set_schedules(h, act))) return rc;
                 h->n_compactions++;
             }
-            prev_active = n_active;
+            br.prev_active = n_active;
         }
-        if (k >= o.max_iter) {
-            st_all = HPRLP_ITER_LIMIT;
+        if (br.k >= o.max_iter) {
+            br.st_all = HPRLP_ITER_LIMIT;
+            br.done = true;
             break;
         }
-        if (o.time_limit > 0 && (now_ms() - t_start) / 1000.0 >= o.time_limit) {
-            st_all = HPRLP_TIME_LIMIT;
+        if (o.time_limit > 0 && t_chunk / 1000.0 >= o.time_limit) {
+            br.st_all = HPRLP_TIME_LIMIT;
+            br.done = true;
             break;
         }
         if (h->prec == 1) {
             // as for one LP, on the largest rel. KKT over the instances still iterating
             bool sw = n_above == 0;
-            kkt_hist.push_back(max_kkt);
-            const size_t S = (size_t)o.stall_checks, H = kkt_hist.size();
+            br.kkt_hist.push_back(max_kkt);
+            const size_t S = (size_t)o.stall_checks, H = br.kkt_hist.size();
             if (!sw && S > 0 && H > S) {
-                const double before = *std::min_element(kkt_hist.begin(), kkt_hist.end() - S);
-                const double recent = *std::min_element(kkt_hist.end() - S, kkt_hist.end());
+                const double before = *std::min_element(br.kkt_hist.begin(), br.kkt_hist.end() - S);
+                const double recent = *std::min_element(br.kkt_hist.end() - S, br.kkt_hist.end());
                 sw = recent > o.stall_ratio * before;
             }
             if (sw && (rc = promote(h))) return rc;
         }
     }
     HIPCHK(h, hipStreamSynchronize(h->st));
-    const double t_end = now_ms();
-    if ((rc = write_outputs(h, x, y, z))) return rc;
-    // per-instance results
+    return HPRLP_OK;
+}
+
+// Per-instance and summed statistics of the batch as it stands.  An instance that stopped
+// reports the time from the start of the solve to the end of the chunk whose check stopped
+// it (t_solve_ms); one still iterating reports the time so far.
+int batch_stats(hprlp_handle *h, int *status) {
+    const hprlp_options &o = h->opt;
+    const int ni = h->n_inst;
+    BatchRun &br = h->br;
+    const double t_end = br.chunk_end.empty() ? br.t_power : br.chunk_end.back().second;
     std::vector<int> ist((size_t)ni);
     std::vector<long long> idone((size_t)ni), irest((size_t)ni), inch((size_t)ni);
-    std::vector<double> isig((size_t)ni), ilast((size_t)ni * 6);
+    std::vector<double> isig((size_t)ni), ilast((size_t)ni * 6), cst((size_t)ni * 8);
+    int rc;
     if ((rc = download(h, ist.data(), h->bd.status, ist.size())) ||
         (rc = download(h, idone.data(), h->bd.iters_done, idone.size())) ||
         (rc = download(h, irest.data(), h->bd.restarts, irest.size())) ||
         (rc = download(h, inch.data(), h->bd.nchecks, inch.size())) ||
         (rc = download(h, isig.data(), h->bd.sigma, isig.size())) ||
-        (rc = download(h, ilast.data(), h->bd.last, ilast.size())))
+        (rc = download(h, ilast.data(), h->bd.last, ilast.size())) ||
+        (rc = download(h, cst.data(), h->bd.cst, cst.size())))
         return rc;
     h->inst_stats.assign((size_t)ni, hprlp_stats_t{});
-    std::vector<double> cst((size_t)ni * 8);
-    if ((rc = download(h, cst.data(), h->bd.cst, cst.size()))) return rc;
-    hprlp_stats_t &s = h->stats;
+    hprlp_stats_t s{};
     int worst = HPRLP_OPTIMAL;
     for (int b = 0; b < ni; ++b) {
         hprlp_stats_t &q = h->inst_stats[b];
-        q.status = ist[b] ? ist[b] : st_all;
-        q.iters = ist[b] ? idone[b] : k;
+        q.status = ist[b] ? ist[b] : br.st_all;
+        q.iters = ist[b] ? idone[b] : br.k;
         q.restarts = irest[b];
         q.sigma = isig[b];
-        q.lambda = lam[b];
-        q.power_iters = piters;
+        q.lambda = br.lam[b];
+        q.power_iters = br.piters;
         q.rel_p = ilast[b * 6 + 0]; q.rel_d = ilast[b * 6 + 1]; q.rel_gap = ilast[b * 6 + 2];
         q.pobj = ilast[b * 6 + 3]; q.dobj = ilast[b * 6 + 4];
         q.beta_b = cst[(size_t)b * 8 + 0];
         q.beta_c = cst[(size_t)b * 8 + 1];
-        q.t_solve_ms = t_end - t_start;
-        q.t_power_ms = t_power;
+        q.t_solve_ms = t_end;
+        if (ist[b])
+            for (const auto &ce : br.chunk_end)
+                if (ce.first == idone[b]) {
+                    q.t_solve_ms = ce.second;
+                    break;
+                }
+        q.t_power_ms = br.t_power;
         q.n_checks = inch[b];
         if (q.status != HPRLP_OPTIMAL && worst == HPRLP_OPTIMAL) worst = q.status;
         s.restarts += q.restarts;
@@ -2009,21 +2108,35 @@ int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status)
         s.pobj += q.pobj;
         s.dobj += q.dobj;
     }
-    h->solved = true;
-    s.iters = k;
-    s.iters_fp32 = h->f32phase ? iters_fp32 : 0;
+    s.iters = br.k;
+    s.iters_fp32 = h->f32phase ? br.iters_fp32 : 0;
     s.status = worst;
-    s.power_iters = piters;
-    s.t_power_ms = t_power;
-    s.t_solve_ms = t_end - t_start;
+    s.power_iters = br.piters;
+    s.t_power_ms = br.t_power;
+    s.t_solve_ms = t_end;
     s.bytes_per_iter = bytes_per_iter(h);
-    s.n_checks = k / o.check_every;
+    s.col_pass_ms = br.prof_ms[0];
+    s.row_pass_ms = br.prof_ms[1];
+    s.col_pass_launches = br.prof_n[0];
+    s.row_pass_launches = br.prof_n[1];
+    s.n_checks = br.k / o.check_every;
     s.n_compactions = h->n_compactions;
     s.t_setup_ms = h->t_setup_ms;
     s.t_prep_ms = h->t_prep_ms;
     s.t_tune_ms = h->t_tune_ms;
+    h->stats = s;
     if (status) *status = worst;
     return HPRLP_OK;
+}
+
+int solve_batched(hprlp_handle *h, double *x, double *y, double *z, int *status) {
+    int rc;
+    if ((rc = batch_begin(h, status))) return rc;
+    if (!h->br.begun) return HPRLP_OK;  // lambda <= 0: status NUMERICAL already reported
+    if ((rc = batch_run(h, -1))) return rc;
+    if ((rc = write_outputs(h, x, y, z))) return rc;
+    h->solved = true;
+    return batch_stats(h, status);
 }
 
 }  // namespace
@@ -2149,10 +2262,51 @@ extern "C" int hprlp_get_schedule(const hprlp_handle *hc, int matrix, int32_t *p
     return HPRLP_OK;
 }
 
+extern "C" int hprlp_begin(hprlp_handle *h) {
+    if (!h) return fail(h, HPRLP_EINVAL, "null handle");
+    int st = 0, rc;
+    if (h->batched) {
+        if ((rc = batch_begin(h, &st))) return rc;
+        if (!h->br.begun) return HPRLP_OK;  // NUMERICAL in the stats; hprlp_step refuses
+        h->solved = true;
+        return batch_stats(h, nullptr);
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const double t0 = now_ms();
+    int piters = 0;
+    if ((rc = single_begin(h, &st, &piters))) return rc;
+    if (h->stats.status == HPRLP_NUMERICAL) return HPRLP_OK;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->solved = true;
+    h->stats.power_iters = piters;
+    h->stats.lambda = h->opt.t1_zero ? 0.0 : h->lambda;
+    h->stats.sigma = h->sigma;
+    h->stats.t_power_ms = now_ms() - t0;
+    h->stats.t_setup_ms = h->t_setup_ms;
+    h->stats.t_prep_ms = h->t_prep_ms;
+    h->stats.t_tune_ms = h->t_tune_ms;
+    return HPRLP_OK;
+}
+
 extern "C" int hprlp_step(hprlp_handle *h, int iters) {
     if (!h || iters < 0) return fail(h, HPRLP_EINVAL, "bad argument");
-    if (h->batched) return fail(h, HPRLP_EINVAL, "hprlp_step is for single-LP handles");
-    if (!h->solved) return fail(h, HPRLP_ESTATE, "call after a solve");
+    if (!h->solved) return fail(h, HPRLP_ESTATE, "call after hprlp_begin or a solve");
+    if (h->batched) {
+        const long long ce = h->opt.check_every;
+        if (iters % ce != 0)
+            return fail(h, HPRLP_EINVAL, "a batched step runs whole chunks: iters must be a "
+                                         "multiple of check_every");
+        if (!h->br.begun) return fail(h, HPRLP_ESTATE, "call after hprlp_begin or a solve");
+        // nothing left to run once every instance has stopped or a limit is reached
+        const hprlp_options &o = h->opt;
+        const bool timed_out =
+            o.time_limit > 0 && (now_ms() - h->br.t_start) / 1000.0 >= o.time_limit;
+        if (h->br.prev_active == 0.0 || h->br.k >= o.max_iter || timed_out) return HPRLP_OK;
+        h->br.done = false;
+        int rc = batch_run(h, iters / ce);
+        if (rc) return rc;
+        return batch_stats(h, nullptr);
+    }
     size_t ev = 0;
     for (int i = 0; i < iters; ++i) {
         const int rc = run_iteration(h, false, nullptr, &ev);

@@ -29,7 +29,7 @@ BATCH_TRACE_COLS = ["k", "t", "r", "sigma", "merit", "rel_p", "rel_d", "rel_gap"
 EXPORTS = ["hprlp_default_options", "hprlp_workspace_bytes", "hprlp_workspace_bytes_batched",
            "hprlp_create", "hprlp_create_batched", "hprlp_solve", "hprlp_stats",
            "hprlp_stats_instance", "hprlp_get_iterate", "hprlp_get_trace",
-           "hprlp_get_trace_instance", "hprlp_get_schedule", "hprlp_step",
+           "hprlp_get_trace_instance", "hprlp_get_schedule", "hprlp_begin", "hprlp_step",
            "hprlp_time_passes", "hprlp_last_error", "hprlp_destroy"]
 
 
@@ -104,6 +104,7 @@ def load() -> C.CDLL:
                                              C.POINTER(C.c_longlong)]
     lib.hprlp_get_schedule.argtypes = [P, C.c_int, P, P, C.POINTER(C.c_double)]
     lib.hprlp_solve.argtypes = [P, P, P, P, C.POINTER(C.c_int)]
+    lib.hprlp_begin.argtypes = [P]
     lib.hprlp_step.argtypes = [P, C.c_int]
     lib.hprlp_stats.argtypes = [P, C.POINTER(Stats)]
     lib.hprlp_get_iterate.argtypes = [P, C.c_int, P]
@@ -284,8 +285,15 @@ class Solver:
                  chunks=int(counts[3]), tuned_ms=ms.value)
         return d
 
+    def begin(self) -> dict:
+        """Start a solve without iterating (lambda, sigma0, the origin); returns the stats."""
+        self._check(self._lib.hprlp_begin(self._h))
+        return self.stats()
+
     def step(self, iters: int):
-        """Run `iters` plain iterations (no checks) from the current state (after a solve)."""
+        """Advance from the current state (after begin or a solve): a single LP runs `iters`
+        plain iterations (no checks); a batch runs iters / check_every whole chunks with
+        their checks and decisions."""
         self._check(self._lib.hprlp_step(self._h, iters))
 
     def time_passes(self, reps: int = 50):

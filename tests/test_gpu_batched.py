@@ -197,3 +197,46 @@ def test_batched_many_small_instances():
     print("many: statuses", {k: sum(s.stats_instance(i)["status"] == k for i in range(n_inst))
                              for k in ("OPTIMAL", "ITER_LIMIT")}, "compactions",
           sol.stats["n_compactions"])
+
+
+def test_begin_step_chunks_equal_solve_and_event_nodes():
+    """hprlp_begin + hprlp_step(k * check_every) runs the same chunks as hprlp_solve: the
+    same w_bar bit for bit, the same per-instance stops, restarts and statuses, and the
+    check-level decisions still match the oracle.  profile = N places HIP event nodes in the
+    chunk graphs; it must not change a bit of the iterates and must time every N-th
+    iteration's passes."""
+    lp = small_batch(5)
+    n_inst = len(lp.inst_m1)
+    iters = 3000
+    refs = [oracle.solve(lp.instance(i), max_iter=iters, check_every=CE) for i in range(n_inst)]
+    lams = [r.lam for r in refs]
+    a = hprlp.Solver(lp, batched=True, lambdas=lams, max_iter=iters, check_every=CE)
+    sa = a.solve()
+    for prof in (0, 10):
+        b = hprlp.Solver(lp, batched=True, lambdas=lams, max_iter=iters, check_every=CE,
+                         profile=prof)
+        st0 = b.begin()
+        assert st0["iters"] == 0
+        for _ in range(iters // (3 * CE)):
+            b.step(3 * CE)
+        st = b.stats()
+        assert st["iters"] <= iters
+        x, y, z = (b.iterate(w) for w in (hprlp.XBAR, hprlp.YBAR, hprlp.ZBAR))
+        np.testing.assert_array_equal(x, sa.x)
+        np.testing.assert_array_equal(y, sa.y)
+        np.testing.assert_array_equal(z, sa.z)
+        for i, ref in enumerate(refs):
+            si = b.stats_instance(i)
+            assert si["iters"] == ref.iters and si["restarts"] == ref.restarts, i
+            assert si["status"] == ref.status, i
+            assert 0 < si["t_solve_ms"] <= st["t_solve_ms"] + 1e-9
+        if prof:
+            chunks = st["iters"] // CE
+            assert st["col_pass_launches"] == st["row_pass_launches"] == chunks * (CE // prof)
+            assert st["col_pass_ms"] > 0 and st["row_pass_ms"] > 0
+        else:
+            assert st["col_pass_launches"] == 0
+        with pytest.raises(hprlp.HPRLPError):
+            b.step(CE + 1)  # a batch steps in whole chunks
+        b.close()
+    a.close()
