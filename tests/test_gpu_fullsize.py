@@ -2,11 +2,19 @@
 (schedules picked by the autotuner, batch256 with check_every = 100).
 
 The oracle runs the same iterations on the CPU (about 29 iterations/s on zipf1m on one
-core), so the first 100 iterations are compared element by element.  Both sides use
-lambda = 1: after the Pock-Chambolle pass lambda_1(A~ A~^T) <= 1 (pinned by the oracle
-tests), so 1 is a valid lambda of the method, and the oracle's power method at these
-sizes would take minutes.  The mixed-precision workloads are checked on their FP64-phase
-kernels (FP32 A, FP64 vectors), which give FP64 iterates.
+core), so the first 100 iterations are compared:
+  * x_bar, y_bar, z_bar, x_cur, y_cur norm-wise to 1e-10 relative, and entry by entry to
+    1e-10 (|ref_i| + 1e-3 ||ref||_inf) (small entries, such as duals of slack rows, get the
+    absolute floor only);
+  * the check trace (checks every 50 iterations, so the first check restarts and updates
+    sigma): k, t, r and the restart decision exactly; sigma, the merits R~ and R~_{r,0}, the
+    residuals of Section 4.1, the objectives and the SigmaUpdate inputs Delta_x, Delta_y,
+    err_p, err_d to 1e-9 relative.
+Both sides use lambda = 1 there: after the Pock-Chambolle pass lambda_1(A~ A~^T) <= 1 (pinned
+by the oracle tests), so 1 is a valid lambda of the method.  The power method itself is
+compared at full size on a fixed count of 50 iterations (power_tol = 0).  The
+mixed-precision workloads are checked on their FP64-phase kernels (FP32 A, FP64 vectors),
+which give FP64 iterates.
 """
 import numpy as np
 import pytest
@@ -17,28 +25,49 @@ from paper_2408_12179_amd import hprlp
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
+CE = 50  # check period of the full-size parity runs: checks (and a restart) at 50 and 100
+TRACE_EXACT = [0, 1, 2, 16]                    # k, t, r, restarted
+TRACE_REL = [3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 17]
+
 
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
 
 
+def close_entrywise(name, a, b, tol=1e-10):
+    scale = np.abs(b) + 1e-3 * np.max(np.abs(b))
+    err = np.abs(a - b) / np.where(scale > 0, scale, 1.0)
+    worst = int(np.argmax(err))
+    assert err[worst] <= tol, (name, worst, a[worst], b[worst], err[worst])
+
+
+def compare_traces(name, got, ref, cols_exact=TRACE_EXACT, cols_rel=TRACE_REL):
+    assert got.shape == ref.shape, (name, got.shape, ref.shape)
+    for c in cols_exact:
+        np.testing.assert_array_equal(got[:, c], ref[:, c], err_msg=f"{name} col {c}")
+    for c in cols_rel:
+        np.testing.assert_allclose(got[:, c], ref[:, c], rtol=1e-9, atol=1e-300,
+                                   err_msg=f"{name} col {c}")
+
+
 def _single(name, iters, precision):
     lp = lpgen.make(name)
-    ref = oracle.solve(lp, max_iter=iters, lambda_override=1.0)
-    s = hprlp.Solver(lp, max_iter=iters, lambda_override=1.0, autotune=1, precision=precision)
+    ref = oracle.solve(lp, max_iter=iters, lambda_override=1.0, check_every=CE)
+    s = hprlp.Solver(lp, max_iter=iters, lambda_override=1.0, autotune=1, precision=precision,
+                     check_every=CE)
     sol = s.solve()
     assert sol.stats["iters"] == ref.iters == iters
-    out = dict(x_bar=rel(sol.x, ref.x), y_bar=rel(sol.y, ref.y), z_bar=rel(sol.z, ref.z),
-               x_cur=rel(s.iterate(hprlp.XCUR), ref.x_cur),
-               y_cur=rel(s.iterate(hprlp.YCUR), ref.y_cur))
+    pairs = dict(x_bar=(sol.x, ref.x), y_bar=(sol.y, ref.y), z_bar=(sol.z, ref.z),
+                 x_cur=(s.iterate(hprlp.XCUR), ref.x_cur),
+                 y_cur=(s.iterate(hprlp.YCUR), ref.y_cur))
+    out = {k: rel(a, b) for k, (a, b) in pairs.items()}
     print(name, s.schedule(0), s.schedule(1), {k: f"{v:.2e}" for k, v in out.items()})
     for k, v in out.items():
         assert v <= 1e-10, (name, k, v)
-    # a sample of single entries, relative to the vector's scale
-    rng = np.random.default_rng(5)
-    idx = rng.integers(0, lp.n, 1000)
-    assert np.max(np.abs(sol.x[idx] - ref.x[idx])) <= 1e-10 * max(np.max(np.abs(ref.x)), 1.0)
+    for k, (a, b) in pairs.items():
+        close_entrywise(f"{name} {k}", a, b)
+    compare_traces(name, s.trace(), ref.trace)
     s.close()
 
 
@@ -71,6 +100,42 @@ def test_fullsize_batch256_sampled_instances():
         ex, ey, ez = rel(sol.x[c0:c1], ref.x), rel(sol.y[r0:r1], ref.y), rel(sol.z[c0:c1], ref.z)
         print("batch256 instance", i, inst.m, inst.n, f"{ex:.2e} {ey:.2e} {ez:.2e}")
         assert max(ex, ey, ez) <= 1e-10, (i, ex, ey, ez)
+        for nm, a, b in (("x", sol.x[c0:c1], ref.x), ("y", sol.y[r0:r1], ref.y),
+                         ("z", sol.z[c0:c1], ref.z)):
+            close_entrywise(f"instance {i} {nm}", a, b)
+        # batched trace columns: k, t, r, sigma, merit, rel_p, rel_d, rel_gap, restarted,
+        # sigma_next  <->  oracle columns 0, 1, 2, 3, 4, 7, 8, 9, 16, 17
+        got = s.trace_instance(i)
+        want = ref.trace[:, [0, 1, 2, 3, 4, 7, 8, 9, 16, 17]]
+        compare_traces(f"instance {i}", got, want, cols_exact=[0, 1, 2, 8],
+                       cols_rel=[3, 4, 5, 6, 7, 9])
+    s.close()
+
+
+def test_fullsize_power_method_zipf1m():
+    """lambda after exactly 50 power iterations (Section 4.1) on the full zipf1m."""
+    lp = lpgen.make("zipf1m")
+    ref = oracle.solve(lp, max_iter=1, power_max_iter=50, power_tol=0.0)
+    s = hprlp.Solver(lp, max_iter=1, power_max_iter=50, power_tol=0.0, autotune=1)
+    st = s.solve().stats
+    print("zipf1m lambda", st["lambda"], ref.lam, st["power_iters"], ref.power_iters)
+    assert st["power_iters"] == ref.power_iters == 50
+    assert abs(st["lambda"] - ref.lam) <= 1e-10 * ref.lam
+    s.close()
+
+
+def test_fullsize_power_method_batch256():
+    """Per-instance lambda after exactly 50 power iterations of the batched power method,
+    against the oracle's power method on sampled instances alone."""
+    lp = lpgen.make("batch256")
+    n_inst = len(lp.inst_m1)
+    s = hprlp.Solver(lp, batched=True, max_iter=100, check_every=100, power_max_iter=50,
+                     power_tol=0.0, autotune=1)
+    s.solve()
+    for i in (0, 117, n_inst - 1):
+        ref = oracle.solve(lp.instance(i), max_iter=1, power_max_iter=50, power_tol=0.0)
+        lam = s.stats_instance(i)["lambda"]
+        assert abs(lam - ref.lam) <= 1e-10 * ref.lam, (i, lam, ref.lam)
     s.close()
 
 
