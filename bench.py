@@ -298,7 +298,7 @@ def run_batched(args):
     }
 
     # ---- time to tolerance: one capped solve from the origin on the same handle
-    if time.perf_counter() + args.ttt_cap + 20 < deadline:
+    if not args.no_ttt and time.perf_counter() + args.ttt_cap + 20 < deadline:
         log(f"time to tolerance: solve capped at {args.ttt_cap:.0f}s")
         solver.solve()
         out["time_to_tol"] = dict(ttt_fields(solver, lp, t_create), cap_s=args.ttt_cap,
@@ -570,6 +570,8 @@ def main():
     ap.add_argument("--setup-on-host", action="store_true",
                     help="preprocess on the host instead of the GPU (bit-identical arrays)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true",
+                    help="batch256: skip the time-to-tolerance solve (profiling runs)")
     ap.add_argument("--no-profile", action="store_true",
                     help="single-LP configs: no HIP events around sampled pass launches")
     args = ap.parse_args()

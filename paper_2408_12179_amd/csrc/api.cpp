@@ -138,6 +138,7 @@ struct hprlp_handle {
     std::vector<hprlp_stats_t> inst_stats;
     BatchRun br;                               // state of the batched run in progress
     bool no_graph_events = false;              // profile: event nodes could not be captured
+    std::string graph_event_error;             // why event nodes were refused, if they were
     // schedule parameters of A and A^T (the autotuner may pick different ones per matrix)
     ScheduleParams spA{}, spT{};
     double tuned_ms[2] = {0.0, 0.0};          // autotuner: best row / column pass time
@@ -1847,15 +1848,66 @@ int set_schedules(hprlp_handle *h, const std::vector<int> &keep) {
     return HPRLP_OK;
 }
 
-// Event record during stream capture: an event node in the captured graph (its timestamp is
-// taken each time the graph runs); outside capture a plain record.
-hipError_t record_event(hipEvent_t ev, hipStream_t st) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(st, &cs);
-    if (e != hipSuccess) return e;
-    if (cs == hipStreamCaptureStatusActive) return hipEventRecordWithFlags(ev, st, hipEventRecordExternal);
-    return hipEventRecord(ev, st);
-}
+// A chunk graph with event nodes.  Stream capture does not turn an event record into a
+// graph node here, so the graph is assembled by hand: the launches between two marks are
+// captured into a segment graph, appended as a child node, and each mark appends an event
+// record node; all nodes form one chain, in launch order.
+struct ChunkBuilder {
+    hipStream_t st;
+    hipGraph_t g = nullptr;
+    hipGraphNode_t last = nullptr;
+    bool capturing = false;
+    hipError_t start() {
+        hipError_t e = hipGraphCreate(&g, 0);
+        if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        capturing = e == hipSuccess;
+        return e;
+    }
+    // end the open capture and append its graph (if it has nodes) as a child node
+    hipError_t close_segment() {
+        hipGraph_t seg = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &seg);
+        capturing = false;
+        if (e != hipSuccess) return e;
+        size_t nn = 0;
+        e = hipGraphGetNodes(seg, nullptr, &nn);
+        if (e == hipSuccess && nn > 0) {
+            hipGraphNode_t node = nullptr;
+            e = hipGraphAddChildGraphNode(&node, g, last ? &last : nullptr, last ? 1 : 0, seg);
+            if (e == hipSuccess) last = node;
+        }
+        (void)hipGraphDestroy(seg);
+        return e;
+    }
+    hipError_t mark(hipEvent_t ev) {
+        hipError_t e = close_segment();
+        hipGraphNode_t node = nullptr;
+        if (e == hipSuccess)
+            e = hipGraphAddEventRecordNode(&node, g, last ? &last : nullptr, last ? 1 : 0, ev);
+        if (e == hipSuccess) {
+            last = node;
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            capturing = e == hipSuccess;
+        }
+        return e;
+    }
+    hipError_t finish(hipGraph_t *out) {
+        hipError_t e = close_segment();
+        if (e == hipSuccess) {
+            *out = g;
+            g = nullptr;
+        }
+        return e;
+    }
+    ~ChunkBuilder() {
+        if (capturing) {
+            hipGraph_t seg = nullptr;
+            (void)hipStreamEndCapture(st, &seg);
+            if (seg) (void)hipGraphDestroy(seg);
+        }
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
 
 // Iterations of a chunk whose passes are bracketed by events (profile = N: every N-th).
 int profiled_iters(const hprlp_handle *h) {
@@ -1867,26 +1919,24 @@ int profiled_iters(const hprlp_handle *h) {
 // + its check sums, plain iterations, last iteration (keep) + check sums, the decisions of
 // every instance, the restart copies, and the iteration counter advance.  With profile = N,
 // the passes of every N-th iteration are bracketed by events 3q, 3q+1 (after the column
-// pass) and 3q+2 (after the row pass) of the event pool.
-int record_chunk(hprlp_handle *h, int prec) {
+// pass) and 3q+2 (after the row pass) of the event pool, marked through `cb`.
+int record_chunk(hprlp_handle *h, int prec, ChunkBuilder *cb) {
     const int L = (int)h->opt.check_every;
-    const int N = profiled_iters(h) > 0 ? h->opt.profile : 0;
+    const int N = cb && profiled_iters(h) > 0 ? h->opt.profile : 0;
     const void *vs = prec == 1 ? static_cast<const void *>(&h->v32)
                                : static_cast<const void *>(&h->v64);
     const IterScalars unused{};  // batched passes read their scalars from device memory
-    for (int q = 0; q < 3 * profiled_iters(h); ++q)
-        if (!pool_event(h, (size_t)q)) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
     hipError_t e = hipSuccess;
     for (int i = 0; i < L && e == hipSuccess; ++i) {
         const bool keep = (i == 0 || i == L - 1);
         const bool samp = N > 0 && i % N == 0;
         const size_t e0 = samp ? (size_t)(3 * (i / N)) : 0;
         const BatchArgs ba = batch_args(h, i);
-        if (samp) e = record_event(h->ev_pool[e0], h->st);
+        if (samp) e = cb->mark(h->ev_pool[e0]);
         if (e == hipSuccess) e = launch_col_pass(prec, keep, h->T, vs, unused, h->st, nullptr, &ba);
-        if (e == hipSuccess && samp) e = record_event(h->ev_pool[e0 + 1], h->st);
+        if (e == hipSuccess && samp) e = cb->mark(h->ev_pool[e0 + 1]);
         if (e == hipSuccess) e = launch_row_pass(prec, keep, h->A, vs, unused, h->st, nullptr, &ba);
-        if (e == hipSuccess && samp) e = record_event(h->ev_pool[e0 + 2], h->st);
+        if (e == hipSuccess && samp) e = cb->mark(h->ev_pool[e0 + 2]);
         if (e == hipSuccess && keep) {
             double *res = i == 0 ? h->bd.res_first : h->bd.res_chk;
             e = launch_check_row(prec, h->A, vs, h->chk, h->v64.bd, 0, h->partsA, res, h->st,
@@ -1920,20 +1970,35 @@ int record_chunk(hprlp_handle *h, int prec) {
 // The chunk graph of one precision phase, captured on first use and kept with the handle.
 int get_graph(hprlp_handle *h, int prec, hipGraphExec_t *out) {
     if (!h->graphs[prec]) {
-        HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
-        const int rc = record_chunk(h, prec);
         hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(h->st, &g);
-        if (rc || e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            if (profiled_iters(h) > 0) {  // event nodes refused: capture without them
+        if (profiled_iters(h) > 0) {
+            // the events of the event nodes exist before the capture starts
+            for (int q = 0; q < 3 * profiled_iters(h); ++q)
+                if (!pool_event(h, (size_t)q)) return fail(h, HPRLP_EHIP, "hipEventCreate failed");
+            ChunkBuilder cb{h->st};
+            hipError_t e = cb.start();
+            int rc = e == hipSuccess ? record_chunk(h, prec, &cb) : HPRLP_OK;
+            if (e == hipSuccess && rc == HPRLP_OK) e = cb.finish(&g);
+            if (e != hipSuccess || rc != HPRLP_OK) {  // event nodes refused: a graph without
+                h->graph_event_error = rc ? h->err : std::string(hipGetErrorString(e));
                 (void)hipGetLastError();
                 h->no_graph_events = true;
-                return get_graph(h, prec, out);
+                if (h->opt.verbose)
+                    std::fprintf(stderr, "hprlp: chunk graph without event nodes (%s)\n",
+                                 h->graph_event_error.c_str());
+                g = nullptr;
             }
-            if (rc) return rc;
         }
-        if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        if (!g) {
+            HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+            const int rc = record_chunk(h, prec, nullptr);
+            const hipError_t e = hipStreamEndCapture(h->st, &g);
+            if (rc || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                if (rc) return rc;
+                return fail(h, HPRLP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            }
+        }
         hipGraphExec_t ex = nullptr;
         const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);

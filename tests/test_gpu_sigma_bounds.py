@@ -87,8 +87,10 @@ def test_bound_kinds_iterate_parity(seed, precision):
     _check_iterates([("x_bar", sol.x, ref.x), ("y_bar", sol.y, ref.y), ("z_bar", sol.z, ref.z),
                      ("x_cur", s.iterate(hprlp.XCUR), ref.x_cur),
                      ("y_cur", s.iterate(hprlp.YCUR), ref.y_cur)])
+    # the box of width 0: x_bar is l~ exactly in the scaled space; unscaling (x = beta_b dc x~
+    # with l~ = l / (dc beta_b)) rounds twice, so the original-space value is within 4 ulp
     fixed = lp.l == lp.u
-    np.testing.assert_array_equal(sol.x[fixed], lp.l[fixed])  # the box of width 0
+    np.testing.assert_allclose(sol.x[fixed], lp.l[fixed], rtol=1e-15, atol=0)
     s.close()
 
 
