@@ -193,6 +193,30 @@ int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
                  const double *b, const double *c, const double *l, const double *u,
                  const hprlp_options *opt, void *d_workspace, size_t ws_bytes, void *stream);
 
+/* hprlp_create for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same create, with the
+ * same arguments except the workspace, whose role is taken by a static scratch array of 64
+ * MiB that the library holds on every GPU it runs on (reserved when the library is loaded
+ * there, kept until the process ends).  The scratch of the CURRENT device is used.  This
+ * call and the handle it returns make no device or pinned-host allocation: no hipMalloc,
+ * hipHostMalloc, captured graph or timing event (so profile and autotune must be 0, else
+ * EINVAL; graph is forced to 0).  Limits and sharing:
+ *   - problems whose hprlp_workspace_bytes exceeds 64 MiB are refused with EINVAL before
+ *     any GPU work (about 7e5 nonzeros for a general LP);
+ *   - single LPs only (no batched variant);
+ *   - one live handle per device: while a handle from this call exists on a device, a second
+ *     call on that device returns ESTATE; hprlp_destroy frees the scratch for the next one.
+ *     The scratch keeps the previous handle's data; create overwrites everything a solve
+ *     reads, so no clearing is needed;
+ *   - every call on one GPU shares that GPU's scratch: calls that overlap on it (a solve
+ *     still running on one stream while another thread creates on the same device after a
+ *     destroy, or one handle used from two threads) race; the guard above only orders
+ *     create and destroy.
+ * Everything else (validation, errors, stream ordering, outputs) is as for hprlp_create. */
+int hprlp_create_noalloc(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
+                         const int64_t *rowptr, const int32_t *colidx, const double *val,
+                         const double *b, const double *c, const double *l, const double *u,
+                         const hprlp_options *opt, void *stream);
 /* Workspace bound for a batch of n_inst LPs packed block-diagonally into m rows, n columns
  * and nnz nonzeros (see hprlp_create_batched).  Host only; EDIM on bad sizes
  * (n_inst must be in [1, min(m, n)]). */

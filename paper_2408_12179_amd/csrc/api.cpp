@@ -16,8 +16,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
+#include <mutex>
 #include <vector>
 
 #include "hprlp_internal.h"
@@ -112,6 +114,7 @@ struct hprlp_handle {
     hipStream_t st = nullptr;       // stream all library work is ordered on
     hipStream_t user_st = nullptr;  // the caller's stream
     bool own_stream = false;
+    bool noalloc = false;                   // created by hprlp_create_noalloc (static scratch)
     hipStream_t cap_st = nullptr;   // single LP: stream the chunk graphs are captured on
     DevMat A, T;
     VecSet<double> v64;
@@ -566,7 +569,12 @@ int upload_common(hprlp_handle *h, const Layout &L,
         h->segT = Segments{h->bd.segT_ptr, h->bd.segT_slots, ni};
     }
     h->pinned_len = std::max<size_t>(4 * kNQ + 64, (size_t)power_cap(o) * L.n_inst);
-    HIPCHK(h, hipHostMalloc((void **)&h->pinned, h->pinned_len * sizeof(double), 0));
+    if (h->noalloc) {  // no HIP allocation: pageable host staging (copies then block)
+        h->pinned = new (std::nothrow) double[h->pinned_len];
+        if (!h->pinned) return fail(h, HPRLP_ENOMEM, "host staging allocation failed");
+    } else {
+        HIPCHK(h, hipHostMalloc((void **)&h->pinned, h->pinned_len * sizeof(double), 0));
+    }
     return HPRLP_OK;
 }
 
@@ -732,7 +740,8 @@ int t1_setup(hprlp_handle *h) {
 int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
                 const int32_t *colidx, const double *val, const double *b, const double *c,
                 const double *l, const double *u, const double *lambda_inst,
-                const hprlp_options *opt, void *d_workspace, size_t ws_bytes, void *stream) {
+                const hprlp_options *opt, void *d_workspace, size_t ws_bytes, void *stream,
+                bool noalloc = false) {
     if (!out) return fail(nullptr, HPRLP_EINVAL, "out is null");
     *out = nullptr;
     const double t_create = now_ms();
@@ -776,6 +785,7 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     h->row_off = L.row_off;
     h->user_st = static_cast<hipStream_t>(stream);
     h->st = h->user_st;
+    h->noalloc = noalloc;
     if (lambda_inst) h->lam_given.assign(lambda_inst, lambda_inst + L.n_inst);
 
     // instance of every row and column
@@ -960,6 +970,32 @@ int workspace_impl(int32_t n_inst, int64_t m, int64_t n, int64_t nnz, const hprl
 
 }  // namespace
 
+// ---------------------------------------------------------------------------- static scratch
+//
+// The workspace of hprlp_create_noalloc: a file-scope device array, one copy per GPU (part
+// of the code object the runtime loads on each device the library runs on, held until the
+// process ends).  Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in symbol): the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and is the only pointer used afterwards.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+const hprlp_handle *g_scratch_owner[kMaxDevices] = {};  // live noalloc handle per device
+int g_scratch_dev_of(const hprlp_handle *h) {
+    for (int d = 0; d < kMaxDevices; ++d)
+        if (g_scratch_owner[d] == h) return d;
+    return -1;
+}
+
+void release_scratch(const hprlp_handle *h) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    const int d = g_scratch_dev_of(h);
+    if (d >= 0) g_scratch_owner[d] = nullptr;
+}
+
 // ============================================================================ C ABI
 
 extern "C" void hprlp_default_options(hprlp_options *o) {
@@ -1042,6 +1078,58 @@ extern "C" int hprlp_create(hprlp_handle **out, int64_t m1, int64_t m2, int64_t 
     Layout L{1, {0, m1 + m2}, {0, n}, {m1}, false};
     return create_impl(out, L, rowptr, colidx, val, b, c, l, u, nullptr, opt, d_workspace,
                        ws_bytes, stream);
+}
+
+extern "C" int hprlp_create_noalloc(hprlp_handle **out, int64_t m1, int64_t m2, int64_t n,
+                                    const int64_t *rowptr, const int32_t *colidx,
+                                    const double *val, const double *b, const double *c,
+                                    const double *l, const double *u,
+                                    const hprlp_options *opt, void *stream) {
+    if (!out) return fail(nullptr, HPRLP_EINVAL, "out is null");
+    *out = nullptr;
+    if (m1 < 0 || m2 < 0 || m1 + m2 < 1 || n < 1)
+        return fail(nullptr, HPRLP_EDIM, "bad dimensions (need m1, m2 >= 0, m1 + m2 >= 1, n >= 1)");
+    if (!rowptr) return fail(nullptr, HPRLP_EINVAL, "rowptr is null");
+    hprlp_options o;
+    if (opt) o = *opt;
+    else hprlp_default_options(&o);
+    // nothing that allocates: no captured graphs, no timing events, no autotuner trials
+    if (o.profile != 0 || o.autotune != 0)
+        return fail(nullptr, HPRLP_EINVAL, "hprlp_create_noalloc needs profile = 0 and autotune = 0");
+    o.graph = 0;
+    const int64_t m = m1 + m2;
+    if (rowptr[m] < 1) return fail(nullptr, HPRLP_EDIM, "A has no nonzero");
+    size_t need = 0;
+    int rc = hprlp_workspace_bytes(m1, m2, n, rowptr[m], &o, &need);
+    if (rc) return rc;
+    if (need > kScratchBytes)
+        return fail(nullptr, HPRLP_EINVAL, "problem needs " + std::to_string(need) +
+                                               " workspace bytes, above the static scratch of " +
+                                               std::to_string(kScratchBytes));
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, HPRLP_EHIP, "hipGetDevice failed");
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch_owner[dev])
+            return fail(nullptr, HPRLP_ESTATE, "the static scratch of this device is in use by "
+                                               "a live hprlp_create_noalloc handle");
+        if (!g_scratch_ptr[dev]) {
+            const hipError_t e = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !g_scratch_ptr[dev]) {
+                g_scratch_ptr[dev] = nullptr;
+                return fail(nullptr, HPRLP_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                                     hipGetErrorString(e));
+            }
+        }
+        ptr = g_scratch_ptr[dev];
+        Layout L{1, {0, m}, {0, n}, {m1}, false};
+        rc = create_impl(out, L, rowptr, colidx, val, b, c, l, u, nullptr, &o, ptr,
+                         kScratchBytes, stream, true);
+        if (rc == HPRLP_OK) g_scratch_owner[dev] = *out;
+    }
+    return rc;
 }
 
 extern "C" int hprlp_create_batched(hprlp_handle **out, int32_t n_inst,
@@ -2432,7 +2520,11 @@ extern "C" void hprlp_destroy(hprlp_handle *h) {
     for (hipGraphExec_t g : h->graphs)
         if (g) (void)hipGraphExecDestroy(g);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-    if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->pinned) {
+        if (h->noalloc) delete[] h->pinned;
+        else (void)hipHostFree(h->pinned);
+    }
+    if (h->noalloc) release_scratch(h);
     if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
     if (h->cap_st) (void)hipStreamDestroy(h->cap_st);
     delete h;

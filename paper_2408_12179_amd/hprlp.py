@@ -27,7 +27,8 @@ TRACE_COLS = ["k", "t", "r", "sigma", "merit", "merit0", "merit_prev", "rel_p", 
 BATCH_TRACE_COLS = ["k", "t", "r", "sigma", "merit", "rel_p", "rel_d", "rel_gap", "restart",
                     "sigma_new"]
 EXPORTS = ["hprlp_default_options", "hprlp_workspace_bytes", "hprlp_workspace_bytes_batched",
-           "hprlp_create", "hprlp_create_batched", "hprlp_solve", "hprlp_stats",
+           "hprlp_create", "hprlp_create_noalloc", "hprlp_create_batched", "hprlp_solve",
+           "hprlp_stats",
            "hprlp_stats_instance", "hprlp_get_iterate", "hprlp_get_trace",
            "hprlp_get_trace_instance", "hprlp_get_schedule", "hprlp_begin", "hprlp_step",
            "hprlp_time_passes", "hprlp_last_error", "hprlp_destroy"]
@@ -95,6 +96,8 @@ def load() -> C.CDLL:
                                           C.POINTER(Options), C.POINTER(C.c_size_t)]
     lib.hprlp_create.argtypes = [C.POINTER(P), C.c_int64, C.c_int64, C.c_int64, P, P, P, P, P,
                                  P, P, C.POINTER(Options), P, C.c_size_t, P]
+    lib.hprlp_create_noalloc.argtypes = [C.POINTER(P), C.c_int64, C.c_int64, C.c_int64, P, P,
+                                         P, P, P, P, P, C.POINTER(Options), P]
     lib.hprlp_workspace_bytes_batched.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int64,
                                                   C.POINTER(Options), C.POINTER(C.c_size_t)]
     lib.hprlp_create_batched.argtypes = [C.POINTER(P), C.c_int32, P, P, P, P, P, P, P, P, P, P,
