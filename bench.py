@@ -376,6 +376,8 @@ def run_single(args):
                 profile=50 if sampled else 0, autotune=0 if args.no_autotune else 1,
                 setup_on_host=1 if args.setup_on_host else 0,
                 t1_zero=1 if args.t1_zero else 0)
+    if args.stall_checks is not None:
+        opts["stall_checks"] = args.stall_checks
     t0 = time.perf_counter()
     solver = hprlp.Solver(lp, **opts)
     t_create = time.perf_counter() - t0
@@ -570,6 +572,8 @@ def main():
     ap.add_argument("--setup-on-host", action="store_true",
                     help="preprocess on the host instead of the GPU (bit-identical arrays)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stall-checks", type=int, default=None,
+                    help="MIXED: checks of the FP32-stall rule (0: switch at tol_switch only)")
     ap.add_argument("--no-ttt", action="store_true",
                     help="batch256: skip the time-to-tolerance solve (profiling runs)")
     ap.add_argument("--no-profile", action="store_true",

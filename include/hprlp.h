@@ -65,6 +65,8 @@ typedef enum {
 /* FP64: A~ stored in FP64, FP64 vectors (the plain solver).
  * MIXED: A stored in FP32 (must be exact), FP32 vectors until the relative KKT residual
  *   reaches tol_switch, then FP64 vectors; checks, restart merit and sigma always in FP64.
+ *   In the FP32 phase the iterate is held as FP32 displacements from the FP64 anchor of the
+ *   current outer loop (renewed at every restart), and the returned w_bar is FP64. 
  * FP64_A32: A stored in FP32 (must be exact), FP64 vectors throughout: FP64 results with
  *   8 instead of 12 bytes per nonzero (FP32 x FP64 products are exact in FP64). */
 typedef enum { HPRLP_FP64 = 0, HPRLP_MIXED = 1, HPRLP_FP64_A32 = 2 } hprlp_precision;
@@ -89,7 +91,8 @@ typedef struct {
     double tol_switch;       /* MIXED: switch to FP64 once rel. KKT <= this (default 1e-5) */
     int stall_checks;        /* MIXED: also switch when the best rel. KKT of the FP32 phase */
                              /* has not fallen below stall_ratio x its earlier best over   */
-                             /* this many checks (default 6; 0: off)                       */
+                             /* this many checks (default 0: off; the FP32 phase keeps      */
+                             /* displacements from the FP64 anchor, so it reaches tol_switch) */
     int tile_nnz;            /* schedule: nonzeros staged per tile (0 = default)           */
     int tile_rows;           /* schedule: rows per tile (0 = default)                      */
     int short_max;           /* schedule: longest row kept in tiles (0 = default)          */

@@ -119,6 +119,7 @@ struct hprlp_handle {
     DevMat A, T;
     VecSet<double> v64;
     VecSet<float> v32;
+    DispSet vdisp;                          // MIXED FP32 phase: displacements (aliases v32)
     CheckData chk;
     double *ux = nullptr, *uy = nullptr;     // unscaling of x and y
     int *cperm = nullptr;                   // column renumbering: internal j -> caller's column
@@ -232,6 +233,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         f.sr = cv.arr<float>(m); f.ybar = cv.arr<float>(m); f.dy = cv.arr<float>(m);
         if (p.relax) f.xrel = cv.arr<float>(n);
     }
+    double *q0d = p.f32phase ? cv.arr<double>(n) : nullptr;
     CheckData c;
     c.ro = cv.arr<double>(m); c.rs = cv.arr<double>(m); c.ys = cv.arr<double>(m);
     c.co = cv.arr<double>(n); c.cs = cv.arr<double>(n); c.xs = cv.arr<double>(n);
@@ -315,6 +317,13 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         h->T.rp = T.rp; h->T.ci = T.ci; h->T.va = T.va; h->T.items = T.items;
         h->T.splits = T.splits; h->T.split_part = T.split_part;
         h->v64 = d; h->v32 = f; h->chk = c; h->ux = ux; h->uy = uy; h->vg = vg; h->w = w;
+        if (p.f32phase) {
+            DispSet &ds = h->vdisp;
+            ds.d = d;
+            ds.dxh = f.xhat; ds.dxrel = f.xrel; ds.dy = f.y;
+            ds.q0 = f.cd; ds.q0d = q0d; ds.dl = f.ld; ds.du = f.ud; ds.sc = f.sc;
+            ds.r0 = f.bd; ds.ny0 = f.y0; ds.sr = f.sr;
+        }
         h->cperm = cperm;
         h->hist = hist; h->inv_norm = inv_norm; h->partsA = partsA; h->partsT = partsT;
         h->res = res; h->outv = outv;
@@ -1020,7 +1029,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->sigma_update = 1;
     o->precision = HPRLP_FP64;
     o->tol_switch = 1e-5;
-    o->stall_checks = 6;
+    o->stall_checks = 0;
     o->reorder = 1;
     o->profile = 0;
     o->verbose = 0;
@@ -1175,9 +1184,14 @@ void fill_scalars(const hprlp_handle *h, IterScalars &s) {
     s.rho = h->opt.rho;
 }
 
-const void *cur_set(const hprlp_handle *h) {
-    return h->prec == 1 ? static_cast<const void *>(&h->v32) : static_cast<const void *>(&h->v64);
+// Vectors of the passes: the displacement set in the FP32 phase of MIXED, else the FP64 set.
+const void *pass_set(const hprlp_handle *h, int prec) {
+    return prec == 1 ? static_cast<const void *>(&h->vdisp) : static_cast<const void *>(&h->v64);
 }
+const void *cur_set(const hprlp_handle *h) { return pass_set(h, h->prec); }
+// The checks always run on FP64 vectors (prec 0 or 2): in the FP32 phase the iterations that
+// keep w_bar write it in FP64.
+int check_prec(int prec) { return prec == 1 ? 2 : prec; }
 
 BatchArgs batch_args(const hprlp_handle *h, int iter_off) {
     BatchArgs a;
@@ -1237,10 +1251,11 @@ int run_iteration(hprlp_handle *h, bool keep, std::vector<ProfRec> *prof, size_t
 int run_check(hprlp_handle *h, int slot) {
     double *outr = h->res + (size_t)(2 * slot) * kNQ;
     double *outc = outr + kNQ;
-    hipError_t e = launch_check_row(h->prec, h->A, cur_set(h), h->chk, h->v64.bd, h->m1,
+    const int cp = check_prec(h->prec);
+    hipError_t e = launch_check_row(cp, h->A, pass_set(h, cp), h->chk, h->v64.bd, h->m1,
                                     h->partsA, outr, h->st);
     if (e == hipSuccess)
-        e = launch_check_col(h->prec, h->T, cur_set(h), h->chk, h->v64.cd, h->v64.sc, h->partsT,
+        e = launch_check_col(cp, h->T, pass_set(h, cp), h->chk, h->v64.cd, h->v64.sc, h->partsT,
                              outc, h->st);
     if (e == hipSuccess && h->opt.t1_zero) {
         // T1 = 0: the y block of M is sigma A~A~^T, so the merit's ||dy||^2 becomes
@@ -1335,11 +1350,15 @@ int power_method(hprlp_handle *h, std::vector<double> &lam, int *iters) {
 int zero_state(hprlp_handle *h) {
     const long long n = h->n, m = h->m;
     hipError_t e = hipSuccess;
-    if (h->prec == 1) {
-        for (float *p : {h->v32.xhat, h->v32.x0, h->v32.xrel})
+    if (h->prec == 1) {  // anchors at the origin, zero displacements, the anchor's data
+        for (double *p : {h->v64.x0, h->v64.xbar})
+            if (e == hipSuccess) e = launch_fill(p, n, 0.0, h->st);
+        for (double *p : {h->v64.y0, h->v64.ybar})
+            if (e == hipSuccess) e = launch_fill(p, m, 0.0, h->st);
+        for (float *p : {h->vdisp.dxh, h->vdisp.dxrel})
             if (p && e == hipSuccess) e = launch_fill_f(p, n, 0.f, h->st);
-        for (float *p : {h->v32.y, h->v32.y0})
-            if (e == hipSuccess) e = launch_fill_f(p, m, 0.f, h->st);
+        if (e == hipSuccess) e = launch_fill_f(h->vdisp.dy, m, 0.f, h->st);
+        if (e == hipSuccess) e = launch_anchor(h->A, h->T, h->vdisp, h->st);
     } else {
         for (double *p : {h->v64.xhat, h->v64.x0, h->v64.xrel})
             if (p && e == hipSuccess) e = launch_fill(p, n, 0.0, h->st);
@@ -1354,12 +1373,9 @@ int zero_state(hprlp_handle *h) {
 int restart_copy(hprlp_handle *h) {
     const long long n = h->n, m = h->m;
     hipError_t e;
-    if (h->prec == 1) {
-        e = launch_copy_f(h->v32.x0, h->v32.xbar, n, h->st);
-        if (e == hipSuccess) e = launch_copy_f(h->v32.xhat, h->v32.xbar, n, h->st);
-        if (e == hipSuccess && h->v32.xrel) e = launch_copy_f(h->v32.xrel, h->v32.xbar, n, h->st);
-        if (e == hipSuccess) e = launch_copy_f(h->v32.y0, h->v32.ybar, m, h->st);
-        if (e == hipSuccess) e = launch_copy_f(h->v32.y, h->v32.ybar, m, h->st);
+    if (h->prec == 1) {  // FP32 phase: the anchor moves to w_bar, its data is renewed
+        e = launch_reanchor(h->vdisp, n, m, h->st);
+        if (e == hipSuccess) e = launch_anchor(h->A, h->T, h->vdisp, h->st);
     } else {
         e = launch_copy_d(h->v64.x0, h->v64.xbar, n, h->st);
         if (e == hipSuccess) e = launch_copy_d(h->v64.xhat, h->v64.xbar, n, h->st);
@@ -1371,24 +1387,10 @@ int restart_copy(hprlp_handle *h) {
     return HPRLP_OK;
 }
 
-// MIXED: move the FP32 state (and the last w_bar) to FP64 and continue in FP64.
+// MIXED: continue in FP64 from the FP32 phase's state: x_hat, x_rel and y become anchor +
+// displacement; the anchors and the last w_bar (x_bar, z, dx, y_bar, dy) are FP64 already.
 int promote(hprlp_handle *h) {
-    const long long n = h->n, m = h->m;
-    hipError_t e = hipSuccess;
-    std::pair<double *, const float *> xs[] = {{h->v64.xhat, h->v32.xhat},
-                                                {h->v64.x0, h->v32.x0},
-                                                {h->v64.xbar, h->v32.xbar},
-                                                {h->v64.zint, h->v32.zint},
-                                                {h->v64.dx, h->v32.dx}};
-    std::pair<double *, const float *> ys[] = {{h->v64.y, h->v32.y},
-                                                {h->v64.y0, h->v32.y0},
-                                                {h->v64.ybar, h->v32.ybar},
-                                                {h->v64.dy, h->v32.dy}};
-    for (auto &p : xs)
-        if (e == hipSuccess) e = launch_f2d(p.first, p.second, n, h->st);
-    if (e == hipSuccess && h->v64.xrel) e = launch_f2d(h->v64.xrel, h->v32.xrel, n, h->st);
-    for (auto &p : ys)
-        if (e == hipSuccess) e = launch_f2d(p.first, p.second, m, h->st);
+    const hipError_t e = launch_disp_promote(h->vdisp, h->n, h->m, h->st);
     if (e != hipSuccess) return fail(h, HPRLP_EHIP, hipGetErrorString(e));
     h->prec = 2;
     return HPRLP_OK;
@@ -1403,7 +1405,7 @@ int copy_out(hprlp_handle *h, double *dst, const double *src, long long k) {
 
 // w_bar of the last check, original space, into x, y, z (host or device pointers).
 int write_outputs(hprlp_handle *h, double *x, double *y, double *z) {
-    const bool f32 = h->prec == 1;
+    const bool f32 = false;  // w_bar is kept in FP64 in every phase
     const void *xb = f32 ? (const void *)h->v32.xbar : (const void *)h->v64.xbar;
     const void *yb = f32 ? (const void *)h->v32.ybar : (const void *)h->v64.ybar;
     const void *zb = f32 ? (const void *)h->v32.zint : (const void *)h->v64.zint;
@@ -1625,8 +1627,7 @@ int single_graph(hprlp_handle *h, int prec, int len, hipGraphExec_t *out) {
     if (!h->graphs[prec]) {
         if (!h->cap_st)
             HIPCHK(h, hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking));
-        const void *vs = prec == 1 ? static_cast<const void *>(&h->v32)
-                                   : static_cast<const void *>(&h->v64);
+        const void *vs = pass_set(h, prec);
         const IterScalars unused{};
         HIPCHK(h, hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
@@ -1852,7 +1853,7 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
         }
         h->trace.push_back(row);
         if (h->prec == 1) {
-            // switch to FP64 at tol_switch, or when FP32 rounding stalls the iteration: the
+            // switch to FP64 at tol_switch, or (stall_checks > 0) when the iteration stalls: the
             // best residual of the last stall_checks checks is not below stall_ratio times
             // the best one before them
             bool sw = kkt <= o.tol_switch;
@@ -2011,8 +2012,8 @@ int profiled_iters(const hprlp_handle *h) {
 int record_chunk(hprlp_handle *h, int prec, ChunkBuilder *cb) {
     const int L = (int)h->opt.check_every;
     const int N = cb && profiled_iters(h) > 0 ? h->opt.profile : 0;
-    const void *vs = prec == 1 ? static_cast<const void *>(&h->v32)
-                               : static_cast<const void *>(&h->v64);
+    const void *vs = pass_set(h, prec);
+    const int cp = check_prec(prec);
     const IterScalars unused{};  // batched passes read their scalars from device memory
     hipError_t e = hipSuccess;
     for (int i = 0; i < L && e == hipSuccess; ++i) {
@@ -2027,11 +2028,11 @@ int record_chunk(hprlp_handle *h, int prec, ChunkBuilder *cb) {
         if (e == hipSuccess && samp) e = cb->mark(h->ev_pool[e0 + 2]);
         if (e == hipSuccess && keep) {
             double *res = i == 0 ? h->bd.res_first : h->bd.res_chk;
-            e = launch_check_row(prec, h->A, vs, h->chk, h->v64.bd, 0, h->partsA, res, h->st,
-                                 &ba, &h->segA, 2 * kNQ);
+            e = launch_check_row(cp, h->A, pass_set(h, cp), h->chk, h->v64.bd, 0, h->partsA,
+                                 res, h->st, &ba, &h->segA, 2 * kNQ);
             if (e == hipSuccess)
-                e = launch_check_col(prec, h->T, vs, h->chk, h->v64.cd, h->v64.sc, h->partsT,
-                                     res + kNQ, h->st, &ba, &h->segT, 2 * kNQ);
+                e = launch_check_col(cp, h->T, pass_set(h, cp), h->chk, h->v64.cd, h->v64.sc,
+                                     h->partsT, res + kNQ, h->st, &ba, &h->segT, 2 * kNQ);
         }
     }
     if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("chunk launch: ") + hipGetErrorString(e));
@@ -2047,9 +2048,14 @@ int record_chunk(hprlp_handle *h, int prec, ChunkBuilder *cb) {
     d.active = h->bd.active; d.status = h->bd.status; d.restart_flag = h->bd.restart_flag;
     d.last = h->bd.last; d.trace = h->bd.trace; d.summary = h->bd.summary;
     e = launch_decide(d, h->st);
-    if (e == hipSuccess)
-        e = launch_restart_batched(prec == 1, vs, h->bd.row_off, h->bd.col_off,
-                                   h->bd.restart_flag, h->n_inst, h->st);
+    if (e == hipSuccess && prec == 1) {  // FP32 phase: move the anchors, renew its data
+        e = launch_reanchor_batched(h->vdisp, h->bd.row_off, h->bd.col_off, h->bd.restart_flag,
+                                    h->n_inst, h->st);
+        if (e == hipSuccess) e = launch_anchor(h->A, h->T, h->vdisp, h->st);
+    } else if (e == hipSuccess) {
+        e = launch_restart_batched(false, vs, h->bd.row_off, h->bd.col_off, h->bd.restart_flag,
+                                   h->n_inst, h->st);
+    }
     if (e == hipSuccess) e = launch_advance(h->bd.kbase, L, h->st);
     if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("chunk launch: ") + hipGetErrorString(e));
     return HPRLP_OK;
@@ -2329,36 +2335,40 @@ extern "C" int hprlp_get_iterate(const hprlp_handle *hc, int which, double *out)
     if (!h->solved) return fail(h, HPRLP_ESTATE, "no solve has run yet");
     if (h->batched && which == HPRLP_XCUR)
         return fail(h, HPRLP_EINVAL, "XCUR needs one inner counter; a batch has one per instance");
-    const bool f32 = h->prec == 1;
+    const bool disp = h->prec == 1;  // FP32 phase: current iterate = anchor + displacement
     double *tmp = h->outv;
     hipError_t e = hipSuccess;
     long long len = 0;
-    switch (which) {
+    switch (which) {  // w_bar is FP64 in every phase
     case HPRLP_XBAR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.xbar : h->v64.xbar, f32, h->ux, 0, h->cperm, h->n, h->st);
+        e = launch_scale_out(tmp, h->v64.xbar, false, h->ux, 0, h->cperm, h->n, h->st);
         len = h->n;
         break;
     case HPRLP_YBAR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.ybar : h->v64.ybar, f32, h->uy, 0, nullptr, h->m, h->st);
+        e = launch_scale_out(tmp, h->v64.ybar, false, h->uy, 0, nullptr, h->m, h->st);
         len = h->m;
         break;
     case HPRLP_ZBAR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.zint : h->v64.zint, f32, h->chk.co, 0, h->cperm, h->n, h->st);
+        e = launch_scale_out(tmp, h->v64.zint, false, h->chk.co, 0, h->cperm, h->n, h->st);
         len = h->n;
         break;
     case HPRLP_XCUR: {
         IterScalars s;
         fill_scalars(h, s);
-        e = launch_xcur_out(tmp, f32 ? (const void *)h->v32.x0 : h->v64.x0,
-                            f32 ? (const void *)(h->v32.xrel ? h->v32.xrel : h->v32.xhat)
-                                : (h->v64.xrel ? h->v64.xrel : h->v64.xhat),
-                            f32, s.hx0, s.hx1,
-                            h->ux, 0, h->cperm, h->n, h->st);
+        if (disp)
+            e = launch_anchor_out(tmp, h->v64.x0, h->vdisp.dxrel ? h->vdisp.dxrel : h->vdisp.dxh,
+                                  s.hx1, h->ux, h->cperm, h->n, h->st);
+        else
+            e = launch_xcur_out(tmp, h->v64.x0, h->v64.xrel ? h->v64.xrel : h->v64.xhat, false,
+                                s.hx0, s.hx1, h->ux, 0, h->cperm, h->n, h->st);
         len = h->n;
         break;
     }
     case HPRLP_YCUR:
-        e = launch_scale_out(tmp, f32 ? (const void *)h->v32.y : h->v64.y, f32, h->uy, 0, nullptr, h->m, h->st);
+        if (disp)
+            e = launch_anchor_out(tmp, h->v64.y0, h->vdisp.dy, 1.0, h->uy, nullptr, h->m, h->st);
+        else
+            e = launch_scale_out(tmp, h->v64.y, false, h->uy, 0, nullptr, h->m, h->st);
         len = h->m;
         break;
     default:

@@ -77,6 +77,24 @@ template <class V> struct VecSet {
     V *ybar = nullptr, *dy = nullptr;
 };
 
+// MIXED, FP32 phase: the iterate as FP32 displacements from the FP64 anchor w^{r,0} of the
+// current outer loop (x0, y0 of d), plus the FP32 data derived from the anchor at every
+// restart.  The FP32 pointers alias buffers of the FP32 VecSet (the FP32 copies of c, l, u, b
+// and y0 are not needed in this form); d holds the FP64 anchors, data and check outputs.
+struct DispSet {
+    VecSet<double> d;
+    float *dxh = nullptr;    // x_hat - x0 (gathered by the y-step)
+    float *dxrel = nullptr;  // relaxed point - x0 (rho != 2 only)
+    float *dy = nullptr;     // y - y0 (gathered by the x-step)
+    float *q0 = nullptr;     // sc (A^T y0 - c)
+    double *q0d = nullptr;   // the same in FP64 (for z_bar in the iterations that keep w_bar)
+    float *dl = nullptr, *du = nullptr;  // l - x0, u - x0
+    float *sc = nullptr;     // dc^2
+    float *r0 = nullptr;     // sr (b - A x0)
+    float *ny0 = nullptr;    // -y0
+    float *sr = nullptr;     // dr^2
+};
+
 // Scalars of one pass launch.
 struct IterScalars {
     double sigma;       // sigma_r
@@ -111,8 +129,9 @@ struct CheckData {
 };
 
 // ---------------------------------------------------------------- kernel launchers
-// prec: 0 = FP64 (double A, double vectors, no fold); 1 = MIXED FP32 phase (float A, float
-// vectors, fold); 2 = MIXED FP64 phase (float A, double vectors, fold).
+// prec: 0 = FP64 (double A, double vectors, no fold); 1 = MIXED FP32 phase (float A, FP32
+// displacements, fold; vecset is a DispSet); 2 = MIXED FP64 phase (float A, double vectors,
+// fold).  The check passes take prec 0 or 2 (always FP64 vectors).
 // ev_mid (nullable): recorded between the main SpMV kernel and the split-row finisher.
 // ba (nullable): batched solve, scalars per instance from device memory instead of s.
 hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vecset,
@@ -172,6 +191,17 @@ hipError_t launch_restart_batched(bool f32, const void *vecset, const int *row_o
                                   const int *col_off, const int *restart_flag, int n_inst,
                                   hipStream_t st);
 hipError_t launch_advance(long long *kbase, int chunk, hipStream_t st);
+// MIXED FP32 phase (DispSet): the per-restart FP32 data from the anchor (two FP64 passes);
+// the anchor moved to w_bar and the displacements zeroed (one LP, or the instances flagged
+// by restart_flag); the switch to FP64 (x_hat, x_rel, y = anchor + displacement).
+hipError_t launch_anchor(const DevMat &A, const DevMat &T, const DispSet &v, hipStream_t st);
+hipError_t launch_reanchor(const DispSet &v, long long n, long long m, hipStream_t st);
+hipError_t launch_reanchor_batched(const DispSet &v, const int *row_off, const int *col_off,
+                                   const int *restart_flag, int n_inst, hipStream_t st);
+hipError_t launch_disp_promote(const DispSet &v, long long n, long long m, hipStream_t st);
+// out[perm[i]] = mul[i] * (a[i] + h * d[i]) (a FP64 anchor, d FP32 displacement)
+hipError_t launch_anchor_out(double *out, const double *a, const float *d, double h,
+                             const double *mul, const int *perm, long long n, hipStream_t st);
 // ---------------------------------------------------------------- device preprocessing
 // (prep.hip) The column renumbering, transpose, scaling and data vectors of create, on the
 // GPU, with the same results as the host preprocessing.

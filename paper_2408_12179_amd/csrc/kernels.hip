@@ -472,6 +472,194 @@ template <class M, class V, bool FOLD, bool KEEP, bool B> struct RowOp {
     }
 };
 
+// ------------------------------------------------------------------ MIXED, FP32 phase
+//
+// The FP32 phase keeps the iterate as FP32 displacements from the FP64 anchor w^{r,0} of
+// the current outer loop of Algorithm 2 (the Halpern anchor, renewed at every restart), so
+// FP32 resolution applies to the distance travelled since the last restart, not to |w|:
+// the dual step (b - A x_hat) / (lambda sigma) stays representable when sigma is large.
+// At every restart the FP64 anchor passes below store, in FP32,
+//   q0 = sc (A^T y0 - c),  dl = l - x0,  du = u - x0   (columns)
+//   r0 = sr (b - A x0),    ny0 = -y0                   (rows)
+// and with d* = * - anchor the two half-steps (eqs. update-z/x and update-y-2) read
+//   x-step: dx = hx1 dxh;  dv = dx + sigma (q0 + sc A^T dy);  dxb = clamp(dv, dl, du);
+//           dxh <- 2 dxb - dx (the y-step gathers it)
+//   y-step: dyb = dy + (r0 - sr A dxh) / (lambda sigma), max(dyb, ny0) on inequality rows;
+//           dy <- hy1 (2 dyb - dy)
+// since the Halpern weights sum to one (x - x0 = hx1 (x_hat - x0), y' - y0 = hy1 (y_hat -
+// y0)).  The iterations that keep w_bar write x_bar = x0 + dxb, z = (dxb - dv) / sigma, dx,
+// y_bar = y0 + dyb and dy in FP64, for the checks, which always run in FP64 (z_bar from the
+// FP64 copy of q0).
+template <bool KEEP, bool B> struct DColOp {
+    using Sum = float;
+    using Raw = RawT<float>;
+    static constexpr int NQ = 0;
+    static constexpr bool PREFETCH = true;
+    struct Pre {
+        float xh, q0, dl, du, sc;
+    };
+    const int *__restrict__ ci;
+    const float *__restrict__ va;
+    const float *__restrict__ dyg;
+    float *__restrict__ dxh;
+    float *__restrict__ dxrel;  // nullptr when rho = 2
+    const float *__restrict__ q0;
+    const float *__restrict__ dl;
+    const float *__restrict__ du;
+    const float *__restrict__ sc;
+    const double *__restrict__ x0;
+    const double *__restrict__ q0d;
+    double *__restrict__ xbar;
+    double *__restrict__ zint;
+    double *__restrict__ dx;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, nullptr);
+    }
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return r.a * dyg[r.j]; }
+    __device__ __forceinline__ Pre load(int j) const {
+        return Pre{(dxrel ? dxrel : dxh)[j], q0[j], dl[j], du[j], sc[j]};
+    }
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &p, const PassCtx &c,
+                                          double *) const {
+        const float sigma = (float)c.sigma;
+        const float d = (float)c.hx1 * p.xh;
+        const float dv = d + sigma * (p.q0 + p.sc * g);
+        const float db = clampv(dv, p.dl, p.du);
+        const float dr = 2.f * db - d;
+        dxh[j] = dr;
+        float dh = dr;
+        if (dxrel) {  // uniform
+            dh = (float)c.rho * db + (1.f - (float)c.rho) * d;
+            dxrel[j] = dh;
+        }
+        if (KEEP) {
+            // z_bar = (x_bar - v) / sigma (eq. update-z): 0 where the projection left v
+            // inside the box; at an active bound (dxb - dx) / sigma - (q0 + sc A^T dy) in FP64
+            // with the FP64 q0 (in FP32, dxb - dv cancels to the rounding of sigma q0), with
+            // the sign of the active bound kept
+            double z = 0.0;
+            if (db != dv) {
+                z = ((double)db - (double)d) / c.sigma - (q0d[j] + (double)p.sc * (double)g);
+                if (db == p.dl && db != p.du) z = z > 0.0 ? z : 0.0;
+                else if (db == p.du && db != p.dl) z = z < 0.0 ? z : 0.0;
+            }
+            xbar[j] = x0[j] + (double)db;
+            zint[j] = z;
+            dx[j] = (double)(d - dh);
+        }
+    }
+};
+
+template <bool KEEP, bool B> struct DRowOp {
+    using Sum = float;
+    using Raw = RawT<float>;
+    static constexpr int NQ = 0;
+    static constexpr bool PREFETCH = true;
+    struct Pre {
+        float dy, r0, sr, ny0;
+    };
+    const int *__restrict__ ci;
+    const float *__restrict__ va;
+    const float *__restrict__ dxg;
+    float *__restrict__ dy;
+    const float *__restrict__ r0;
+    const float *__restrict__ sr;
+    const float *__restrict__ ny0;
+    const double *__restrict__ y0;
+    double *__restrict__ ybar;
+    double *__restrict__ dyk;
+    IterScalars s;
+    BatchArgs ba;
+    __device__ __forceinline__ PassCtx begin(int inst) const {
+        return B ? ctx_batch(ba, inst) : ctx_single(s, nullptr);
+    }
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return r.a * dxg[r.j]; }
+    __device__ __forceinline__ Pre load(int i) const { return Pre{dy[i], r0[i], sr[i], ny0[i]}; }
+    __device__ __forceinline__ void apply(int i, Sum s_, const Pre &p, const PassCtx &c,
+                                          double *) const {
+        const float r = p.r0 - p.sr * s_;
+        float db = p.dy + r / (float)c.lam_sigma;
+        if (i >= c.m1_end) db = vmax(db, p.ny0);
+        const float dr = c.rho == 2.0 ? 2.f * db - p.dy
+                                      : (float)c.rho * db + (1.f - (float)c.rho) * p.dy;
+        dy[i] = (float)c.hy1 * dr;
+        if (KEEP) {
+            ybar[i] = y0[i] + (double)db;
+            dyk[i] = (double)(p.dy - dr);
+        }
+    }
+};
+
+// The per-restart FP32 data of the displacement form, computed in FP64 from the anchor
+// (A stored in FP32, FP32 x FP64 products exact in FP64).  Every row / column is written,
+// stopped instances included (their anchor does not move, so their values do not change).
+__device__ __forceinline__ PassCtx ctx_all() {
+    PassCtx c{};
+    c.active = 1;
+    return c;
+}
+
+struct AnchorColOp {
+    using Sum = double;
+    using Raw = RawT<float>;
+    using Pre = NoPre;
+    static constexpr int NQ = 0;
+    static constexpr bool PREFETCH = false;
+    const int *__restrict__ ci;
+    const float *__restrict__ va;
+    const double *__restrict__ y0;
+    const double *__restrict__ cd;
+    const double *__restrict__ sc;
+    const double *__restrict__ ld;
+    const double *__restrict__ ud;
+    const double *__restrict__ x0;
+    float *__restrict__ q0;
+    double *__restrict__ q0d;
+    float *__restrict__ dl;
+    float *__restrict__ du;
+    __device__ __forceinline__ PassCtx begin(int) const { return ctx_all(); }
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return (double)r.a * y0[r.j]; }
+    __device__ __forceinline__ Pre load(int) const { return Pre{}; }
+    __device__ __forceinline__ void apply(int j, Sum g, const Pre &, const PassCtx &,
+                                          double *) const {
+        const double q = sc[j] * (g - cd[j]);
+        q0d[j] = q;
+        q0[j] = (float)q;
+        dl[j] = (float)(ld[j] - x0[j]);
+        du[j] = (float)(ud[j] - x0[j]);
+    }
+};
+
+struct AnchorRowOp {
+    using Sum = double;
+    using Raw = RawT<float>;
+    using Pre = NoPre;
+    static constexpr int NQ = 0;
+    static constexpr bool PREFETCH = false;
+    const int *__restrict__ ci;
+    const float *__restrict__ va;
+    const double *__restrict__ x0;
+    const double *__restrict__ bd;
+    const double *__restrict__ sr;
+    const double *__restrict__ y0;
+    float *__restrict__ r0;
+    float *__restrict__ ny0;
+    __device__ __forceinline__ PassCtx begin(int) const { return ctx_all(); }
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &r) const { return (double)r.a * x0[r.j]; }
+    __device__ __forceinline__ Pre load(int) const { return Pre{}; }
+    __device__ __forceinline__ void apply(int i, Sum s_, const Pre &, const PassCtx &,
+                                          double *) const {
+        r0[i] = (float)(sr[i] * (bd[i] - s_));
+        ny0[i] = (float)(-y0[i]);
+    }
+};
+
 // Check, row side (FP64): p = A x_bar and q = A dx from one pass over A.
 //   q0 = ||Pi_D(b - A x)||^2 (original data)   q1 = same on the scaled data (sigma update)
 //   q2 = <b, y_bar> / (beta_b beta_c)          q3 = ||dy||^2 (scaled)
@@ -801,6 +989,58 @@ __global__ __launch_bounds__(kWG) void k_restart_batched(VecSet<V> v, const int 
     }
 }
 
+// Displacement form: w^{r+1,0} = w_bar (the FP64 anchor moves to the FP64 w_bar of the
+// check) and the current iterate equals it (displacements zero).  One LP: grid-stride over
+// all entries; batched: one workgroup per instance flagged by restart_flag.
+__global__ void k_reanchor(DispSet v, long long n, long long m) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += stride) {
+        v.d.x0[j] = v.d.xbar[j];
+        v.dxh[j] = 0.f;
+        if (v.dxrel) v.dxrel[j] = 0.f;
+    }
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < m; i += stride) {
+        v.d.y0[i] = v.d.ybar[i];
+        v.dy[i] = 0.f;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_reanchor_batched(DispSet v, const int *row_off,
+                                                          const int *col_off,
+                                                          const int *restart_flag) {
+    const int b = blockIdx.x;
+    if (!restart_flag[b]) return;
+    for (int j = col_off[b] + threadIdx.x; j < col_off[b + 1]; j += kWG) {
+        v.d.x0[j] = v.d.xbar[j];
+        v.dxh[j] = 0.f;
+        if (v.dxrel) v.dxrel[j] = 0.f;
+    }
+    for (int i = row_off[b] + threadIdx.x; i < row_off[b + 1]; i += kWG) {
+        v.d.y0[i] = v.d.ybar[i];
+        v.dy[i] = 0.f;
+    }
+}
+
+// Switch to FP64: x_hat, x_rel, y = anchor + displacement (the anchors and the kept w_bar
+// are FP64 already).
+__global__ void k_disp_promote(DispSet v, long long n, long long m) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += stride) {
+        const double x0 = v.d.x0[j];
+        v.d.xhat[j] = x0 + (double)v.dxh[j];
+        if (v.dxrel) v.d.xrel[j] = x0 + (double)v.dxrel[j];
+    }
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < m; i += stride)
+        v.d.y[i] = v.d.y0[i] + (double)v.dy[i];
+}
+
+__global__ void k_anchor_out(double *out, const double *a, const float *d, double h,
+                             const double *mul, const int *perm, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[perm ? perm[i] : i] = mul[i] * (a[i] + h * (double)d[i]);
+}
+
 __global__ void k_advance(long long *kbase, int chunk) { *kbase += chunk; }
 
 // ------------------------------------------------------------------------- launch helpers
@@ -850,6 +1090,32 @@ hipError_t row_pass(const DevMat &A, const VecSet<V> &v, const IterScalars &s, h
     op.va = reinterpret_cast<const M *>(A.va);
     op.xg = v.xhat;
     op.y = v.y; op.y0 = v.y0; op.bd = v.bd; op.sr = v.sr; op.ybar = v.ybar; op.dy = v.dy;
+    set_scalars(op, s, ba);
+    return run_pass(A, op, nullptr, st, ev);
+}
+
+template <bool KEEP, bool B>
+hipError_t dcol_pass(const DevMat &T, const DispSet &v, const IterScalars &s, hipStream_t st,
+                     hipEvent_t ev, const BatchArgs *ba) {
+    DColOp<KEEP, B> op;
+    op.ci = T.ci;
+    op.va = reinterpret_cast<const float *>(T.va);
+    op.dyg = v.dy;
+    op.dxh = v.dxh; op.dxrel = v.dxrel; op.q0 = v.q0; op.dl = v.dl; op.du = v.du; op.sc = v.sc;
+    op.x0 = v.d.x0; op.q0d = v.q0d; op.xbar = v.d.xbar; op.zint = v.d.zint; op.dx = v.d.dx;
+    set_scalars(op, s, ba);
+    return run_pass(T, op, nullptr, st, ev);
+}
+
+template <bool KEEP, bool B>
+hipError_t drow_pass(const DevMat &A, const DispSet &v, const IterScalars &s, hipStream_t st,
+                     hipEvent_t ev, const BatchArgs *ba) {
+    DRowOp<KEEP, B> op;
+    op.ci = A.ci;
+    op.va = reinterpret_cast<const float *>(A.va);
+    op.dxg = v.dxh;
+    op.dy = v.dy; op.r0 = v.r0; op.sr = v.sr; op.ny0 = v.ny0;
+    op.y0 = v.d.y0; op.ybar = v.d.ybar; op.dyk = v.d.dy;
     set_scalars(op, s, ba);
     return run_pass(A, op, nullptr, st, ev);
 }
@@ -989,6 +1255,13 @@ inline dim3 grid_for(long long n) {
 hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vs,
                            const IterScalars &s, hipStream_t st, hipEvent_t ev,
                            const BatchArgs *ba) {
+    if (prec == 1) {
+        const DispSet &v = *static_cast<const DispSet *>(vs);
+        return ba ? (keep ? dcol_pass<true, true>(T, v, s, st, ev, ba)
+                          : dcol_pass<false, true>(T, v, s, st, ev, ba))
+                  : (keep ? dcol_pass<true, false>(T, v, s, st, ev, ba)
+                          : dcol_pass<false, false>(T, v, s, st, ev, ba));
+    }
 #define COL_CALL(M, V, F)                                                                       \
     (ba ? (keep ? col_pass<M, V, F, true, true>(T, v, s, st, ev, ba)                           \
                 : col_pass<M, V, F, false, true>(T, v, s, st, ev, ba))                         \
@@ -1001,6 +1274,13 @@ hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vs,
 hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vs,
                            const IterScalars &s, hipStream_t st, hipEvent_t ev,
                            const BatchArgs *ba) {
+    if (prec == 1) {
+        const DispSet &v = *static_cast<const DispSet *>(vs);
+        return ba ? (keep ? drow_pass<true, true>(A, v, s, st, ev, ba)
+                          : drow_pass<false, true>(A, v, s, st, ev, ba))
+                  : (keep ? drow_pass<true, false>(A, v, s, st, ev, ba)
+                          : drow_pass<false, false>(A, v, s, st, ev, ba));
+    }
 #define ROW_CALL(M, V, F)                                                                       \
     (ba ? (keep ? row_pass<M, V, F, true, true>(A, v, s, st, ev, ba)                           \
                 : row_pass<M, V, F, false, true>(A, v, s, st, ev, ba))                         \
@@ -1065,6 +1345,46 @@ hipError_t launch_restart_batched(bool f32, const void *vs, const int *row_off,
         hipLaunchKernelGGL(k_restart_batched<double>, dim3(n_inst), dim3(kWG), 0, st,
                            *static_cast<const VecSet<double> *>(vs), row_off, col_off,
                            restart_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_anchor(const DevMat &A, const DevMat &T, const DispSet &v, hipStream_t st) {
+    AnchorColOp oc;
+    oc.ci = T.ci;
+    oc.va = reinterpret_cast<const float *>(T.va);
+    oc.y0 = v.d.y0; oc.cd = v.d.cd; oc.sc = v.d.sc; oc.ld = v.d.ld; oc.ud = v.d.ud;
+    oc.x0 = v.d.x0; oc.q0 = v.q0; oc.q0d = v.q0d; oc.dl = v.dl; oc.du = v.du;
+    hipError_t e = run_pass(T, oc, nullptr, st);
+    if (e != hipSuccess) return e;
+    AnchorRowOp orw;
+    orw.ci = A.ci;
+    orw.va = reinterpret_cast<const float *>(A.va);
+    orw.x0 = v.d.x0; orw.bd = v.d.bd; orw.sr = v.d.sr; orw.y0 = v.d.y0;
+    orw.r0 = v.r0; orw.ny0 = v.ny0;
+    return run_pass(A, orw, nullptr, st);
+}
+
+hipError_t launch_reanchor(const DispSet &v, long long n, long long m, hipStream_t st) {
+    hipLaunchKernelGGL(k_reanchor, grid_for(n > m ? n : m), dim3(256), 0, st, v, n, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_reanchor_batched(const DispSet &v, const int *row_off, const int *col_off,
+                                   const int *restart_flag, int n_inst, hipStream_t st) {
+    if (n_inst > 0)
+        hipLaunchKernelGGL(k_reanchor_batched, dim3(n_inst), dim3(kWG), 0, st, v, row_off,
+                           col_off, restart_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_disp_promote(const DispSet &v, long long n, long long m, hipStream_t st) {
+    hipLaunchKernelGGL(k_disp_promote, grid_for(n > m ? n : m), dim3(256), 0, st, v, n, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_anchor_out(double *out, const double *a, const float *d, double h,
+                             const double *mul, const int *perm, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_anchor_out, grid_for(n), dim3(256), 0, st, out, a, d, h, mul, perm, n);
     return hipGetLastError();
 }
 

@@ -3,9 +3,11 @@ against the FP64 oracle.
 
   * FP64_A32 (A in FP32, exact; FP64 vectors): same bar as the FP64 path, 100-iteration
     iterate parity <= 1e-10 (the products are exact in FP64, only summation order differs).
-  * MIXED: FP32 vectors until rel. KKT <= 1e-5, then FP64.  Full solves must reach rel. KKT
-    <= 1e-8 and agree with the oracle's objective to 1e-7 relative; the error of each result
-    against the oracle is printed.
+  * MIXED: FP32 displacements from the FP64 anchor until rel. KKT <= 1e-5, then FP64.  Full
+    solves must reach rel. KKT <= 1e-8 and agree with the oracle's objective to 1e-7
+    relative (the error of each result against the oracle is printed); FP32-phase iterates
+    stay within an FP32 rounding bound of the oracle's over 100 and 1000 iterations; the
+    switch happens at the first check below tol_switch.
 """
 import numpy as np
 import pytest
@@ -67,11 +69,48 @@ def test_mixed_full_solve_against_oracle(name, scale):
     assert max(relative_kkt(lp, sol.x, sol.y, sol.z)) <= 1.5e-8
 
 
-def test_mixed_fp32_phase_tracks_oracle():
-    # 100 FP32 iterations stay close to the FP64 iterates (FP32 rounding only)
-    lp = lpgen.make("tiny")
-    ref = oracle.solve(lp, max_iter=100)
-    s = hprlp.Solver(lp, max_iter=100, lambda_override=ref.lam, precision=hprlp.MIXED)
-    s.solve()
-    assert rel(s.iterate(hprlp.XCUR), ref.x_cur) <= 1e-4
-    assert rel(s.iterate(hprlp.YCUR), ref.y_cur) <= 1e-4
+# FP32 phase against the FP64 oracle.  Each half-step rounds each displacement entry once
+# in FP32 (unit roundoff u = 2^-24); the anchor of every outer loop is FP64, so the error
+# is that of at most one outer loop's FP32 steps, ~150 here (checks every 150 iterations,
+# restarts at checks), two roundings each: 2 * 150 * u ~ 1.8e-5, relative to the iterate.
+FP32_PHASE_BOUND = 2 * 150 * 2.0 ** -24
+
+
+@pytest.mark.parametrize("name,scale", [("tiny", 1), ("zipf1m", 0.004), ("transport10m", 0.01),
+                                        ("batch256", 0.004)])
+@pytest.mark.parametrize("iters", [100, 1000])
+def test_mixed_fp32_phase_iterates_against_oracle(name, scale, iters):
+    lp = lpgen.make(name, scale)
+    if lp.inst_m1 is not None:
+        lp = lp.instance(0)
+    ref = oracle.solve(lp, max_iter=iters, tol=1e-30)
+    s = hprlp.Solver(lp, max_iter=iters, tol=1e-30, lambda_override=ref.lam,
+                     precision=hprlp.MIXED, tol_switch=1e-30)
+    sol = s.solve()
+    assert sol.stats["iters_fp32"] == iters  # never left the FP32 phase
+    assert sol.stats["restarts"] == ref.restarts
+    errs = dict(x_cur=rel(s.iterate(hprlp.XCUR), ref.x_cur),
+                y_cur=rel(s.iterate(hprlp.YCUR), ref.y_cur),
+                x_bar=rel(sol.x, ref.x), y_bar=rel(sol.y, ref.y), z_bar=rel(sol.z, ref.z))
+    print(name, scale, iters, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= FP32_PHASE_BOUND, (k, v)
+
+
+@pytest.mark.parametrize("name,scale", [("transport10m", 0.02), ("zipf1m", 0.004)])
+def test_mixed_hands_over_at_tol_switch(name, scale):
+    """Default options: the FP32 phase runs until a check with rel. KKT <= tol_switch (1e-5)
+    and the FP64 phase then finishes; the switching check is the first one below 1e-5."""
+    lp = lpgen.make(name, scale)
+    s = hprlp.Solver(lp, precision=hprlp.MIXED, max_iter=20000)
+    sol = s.solve()
+    st = sol.stats
+    tr = s.trace()
+    C = {k: i for i, k in enumerate(hprlp.TRACE_COLS)}
+    kkt = np.maximum(np.maximum(tr[:, C["rel_p"]], tr[:, C["rel_d"]]), tr[:, C["rel_gap"]])
+    k32 = st["iters_fp32"]
+    assert 0 < k32 < st["iters"]
+    i = int(np.flatnonzero(tr[:, C["k"]] == k32)[0])
+    assert kkt[i] <= 1e-5 and np.all(kkt[:i] > 1e-5), (k32, kkt[: i + 1])
+    print(name, scale, sol.status, st["iters"], "iterations,", k32, "in FP32; rel. KKT at the "
+          "switch", f"{kkt[i]:.2e}")
