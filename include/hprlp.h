@@ -130,6 +130,15 @@ typedef struct {
                              /* problem on the GPU, in scratch inside the workspace (which  */
                              /* hprlp_workspace_bytes then includes); 1: on the host, with  */
                              /* a smaller workspace.  Both give bit-identical arrays        */
+    int tile_order;          /* order of the nonzeros inside each tile of A and A^T (the    */
+                             /* schedules' runs of short rows): 0 (default) = row order;    */
+                             /* 1 = column order (the gathers of a wavefront then walk the  */
+                             /* gathered vector in increasing address order and share cache */
+                             /* lines; each product is put back in its row-order slot before */
+                             /* the sums, so results are bit-identical; 2 more bytes read   */
+                             /* per nonzero); -1 = chosen per matrix by the autotuner (row  */
+                             /* order when autotune = 0).  Not with t1_zero (EINVAL for 1;  */
+                             /* -1 means row order there)                                    */
 } hprlp_options;
 
 typedef struct {
@@ -317,8 +326,8 @@ int hprlp_get_trace_instance(const hprlp_handle *h, int32_t i, double *out, long
 
 /* Schedule in use for A (matrix = 0, the row pass) or A^T (matrix = 1, the column pass):
  * params[5] = {tile_nnz, tile_rows, short_max, split_len, chunk_nnz} (nullable),
- * counts[4] = {work items incl. padding, tiles, whole-workgroup rows, split chunks}
- * (nullable), *tuned_ms = the autotuner's measured time of one pass launch with it (0 when
+ * counts[5] = {work items incl. padding, tiles, whole-workgroup rows, split chunks,
+ * 1 if the tiles hold their nonzeros in column order (tile_order) else 0} (nullable), *tuned_ms = the autotuner's measured time of one pass launch with it (0 when
  * the autotuner did not run; nullable).  Host only. */
 int hprlp_get_schedule(const hprlp_handle *h, int matrix, int32_t *params, int64_t *counts,
                        double *tuned_ms);

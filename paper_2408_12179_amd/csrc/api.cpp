@@ -195,7 +195,14 @@ struct Plan {
     bool batched;
     bool prep = false;   // scratch of the device preprocessing
     int64_t t1m = 0;     // T1 = 0: rows of the dense inverse of A~A~^T (0: off)
+    bool tile_pos = false;  // tiles may be stored in column order: row-order slots per nonzero
 };
+
+// Column-ordered tiles are possible (forced, or left to the autotuner); never with T1 = 0,
+// whose kernels read A row by row.
+bool tile_pos_needed(const hprlp_options &o) {
+    return !o.t1_zero && (o.tile_order == 1 || (o.tile_order == -1 && o.autotune));
+}
 
 void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     const size_t m = (size_t)p.m, n = (size_t)p.n, nnz = (size_t)p.nnz;
@@ -207,6 +214,10 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     T.rp = cv.arr<int>(n + 1);
     T.ci = cv.arr<int>(nnz);
     T.va = cv.take(nnz * vs);
+    if (p.tile_pos) {
+        A.pos = cv.arr<unsigned short>(nnz);
+        T.pos = cv.arr<unsigned short>(nnz);
+    }
     A.items = cv.arr<int4>((size_t)std::max(p.itemsA, 1));
     T.items = cv.arr<int4>((size_t)std::max(p.itemsT, 1));
     A.splits = cv.arr<int4>((size_t)std::max(p.splitA, 1));
@@ -313,9 +324,9 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         h->prep = ps;
         h->t1 = t1;
         h->A.rp = A.rp; h->A.ci = A.ci; h->A.va = A.va; h->A.items = A.items;
-        h->A.splits = A.splits; h->A.split_part = A.split_part;
+        h->A.splits = A.splits; h->A.split_part = A.split_part; h->A.pos = A.pos;
         h->T.rp = T.rp; h->T.ci = T.ci; h->T.va = T.va; h->T.items = T.items;
-        h->T.splits = T.splits; h->T.split_part = T.split_part;
+        h->T.splits = T.splits; h->T.split_part = T.split_part; h->T.pos = T.pos;
         h->v64 = d; h->v32 = f; h->chk = c; h->ux = ux; h->uy = uy; h->vg = vg; h->w = w;
         if (p.f32phase) {
             DispSet &ds = h->vdisp;
@@ -366,6 +377,7 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n
     p.batched = batched;
     p.prep = !o.setup_on_host;
     p.t1m = (o.t1_zero && !batched) ? m : 0;
+    p.tile_pos = tile_pos_needed(o);
     return p;
 }
 
@@ -712,6 +724,7 @@ int validate_layout(const Layout &L, int64_t m, int64_t n, const int64_t *rowptr
 
 int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
                    const int32_t *inst_row, const int32_t *inst_col);
+int set_tile_order(hprlp_handle *h, bool row, bool col, bool to_col);
 
 // Where the T1 = 0 variant applies: one LP, equality rows only, FP64, a dense inverse of
 // A~A~^T of at most kT1MaxRows rows.
@@ -954,6 +967,7 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     const double t_tune = now_ms();
     if (!rc && o.autotune && nnz >= kTuneMinNnz)
         rc = tune_schedules(h, rowptr, rpt.data(), irow, icol);
+    if (!rc && o.tile_order == 1 && h->A.pos) rc = set_tile_order(h, true, true, true);
     h->t_tune_ms = now_ms() - t_tune;
     if (rc) {
         g_create_error = h->err;
@@ -1037,6 +1051,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->stall_ratio = 0.5;
     o->graph = 1;
     o->rho = 2.0;
+    o->tile_order = 0;
     resolve_options(*o);
 }
 
@@ -1516,6 +1531,19 @@ int time_pass(hprlp_handle *h, bool col, double *ms) {
     return HPRLP_OK;
 }
 
+// Tiles of A (row) and / or A^T (col) to column order (to_col) or back to row order.
+int set_tile_order(hprlp_handle *h, bool row, bool col, bool to_col) {
+    for (int w = 0; w < 2; ++w) {
+        DevMat &M = w ? h->T : h->A;
+        if (!(w ? col : row) || !M.pos || M.sorted == to_col) continue;
+        const hipError_t e = launch_tile_order(M, h->mixed, to_col, h->st);
+        if (e != hipSuccess) return fail(h, HPRLP_EHIP, std::string("tile order: ") + hipGetErrorString(e));
+        M.sorted = to_col;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return HPRLP_OK;
+}
+
 bool same_schedule(const Schedule &a, const Schedule &b) {
     return a.items.size() == b.items.size() && a.splits.size() == b.splits.size() &&
            std::memcmp(a.items.data(), b.items.data(), a.items.size() * sizeof(int4)) == 0 &&
@@ -1612,6 +1640,14 @@ int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
         }
         if ((rc = install_schedule(h, col, std::move(best_s)))) return rc;
         (col ? h->spT : h->spA) = best;
+        // the chosen schedule with its tiles in column order; kept only if >= 3% faster
+        if ((col ? h->T : h->A).pos && h->opt.tile_order == -1) {
+            if ((rc = set_tile_order(h, !col, col, true))) return rc;
+            double ms = 0.0;
+            if ((rc = time_pass(h, col, &ms))) return rc;
+            if (ms < 0.97 * best_ms) best_ms = ms;
+            else if ((rc = set_tile_order(h, !col, col, false))) return rc;
+        }
         h->tuned_ms[w] = best_ms;
     }
     return HPRLP_OK;
@@ -2420,6 +2456,7 @@ extern "C" int hprlp_get_schedule(const hprlp_handle *hc, int matrix, int32_t *p
     if (counts) {
         counts[0] = (int64_t)S.items.size(); counts[1] = S.n_tiles; counts[2] = S.n_rowitems;
         counts[3] = S.n_chunks;
+        counts[4] = (matrix == 0 ? h->A : h->T).sorted ? 1 : 0;
     }
     if (tuned_ms) *tuned_ms = h->tuned_ms[matrix];
     return HPRLP_OK;

@@ -59,7 +59,15 @@ struct DevMat {
     void *split_part = nullptr; // partial sums of split rows (max 16 B per slot)
     int tile_nnz = 0, tile_rows = 0;
     Schedule host;              // kept for stats / re-upload
+    // column-ordered tiles: pos[p] = row-order offset inside its tile of the nonzero stored
+    // at p (allocated when tile_order allows it); `sorted` says whether the tiles are in that
+    // order now.  Whole-workgroup rows and split chunks always keep row order.
+    unsigned short *pos = nullptr;
+    bool sorted = false;
 };
+// Reorder the nonzeros of every tile of M to column order (to_col) or back to row order;
+// values are float (mat_f32) or double.
+hipError_t launch_tile_order(const DevMat &M, bool mat_f32, bool to_col, hipStream_t st);
 
 // Iterate state and per-iteration data vectors in one precision V.
 // Internal coordinates: FP64 mode works on the scaled problem (x~, y~); MIXED works on

@@ -181,12 +181,17 @@ __device__ __forceinline__ typename Op::Sum row_sum(const Op &op, int b, int e, 
     return s;
 }
 
-template <class Op>
+// POS: the tiles hold their nonzeros in column order and pos[p] is the row-order offset
+// (inside its tile) of the nonzero stored at p; each product is staged at that offset, so
+// the sums below see the row order either way.  (A template parameter, so the row-order
+// kernel keeps its registers.)
+template <class Op, bool POS>
 __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
                                               const int *__restrict__ rp, Op op,
                                               typename Op::Sum *__restrict__ split_part,
                                               double *__restrict__ parts, int tile_cap,
-                                              int rows_cap) {
+                                              int rows_cap,
+                                              const unsigned short *__restrict__ pos) {
     using S = typename Op::Sum;
     using Pre = typename Op::Pre;
     constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
@@ -226,13 +231,18 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
                 typename Op::Raw raw[kEPT];
 #pragma unroll
                 for (int u = 0; u < kEPT; ++u) raw[u] = op.raw(P0 + min(tid + u * kWG, cnt - 1));
+                int slot[kEPT];
+#pragma unroll
+                for (int u = 0; u < kEPT; ++u)
+                    slot[u] = POS ? (int)__builtin_nontemporal_load(pos + P0 + min(tid + u * kWG, cnt - 1))
+                                  : tid + u * kWG;
                 S v[kEPT];
 #pragma unroll
                 for (int u = 0; u < kEPT; ++u) v[u] = op.prod(raw[u]);
 #pragma unroll
                 for (int u = 0; u < kEPT; ++u) {
                     const int k = tid + u * kWG;
-                    if (k < cnt) prod[k] = v[u];
+                    if (k < cnt) prod[slot[u]] = v[u];
                 }
             }
 #pragma unroll
@@ -287,6 +297,67 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
         for (int j = 0; j < Op::NQ; ++j) {
             const double t = block_sum(q[j], redq);
             if (tid == 0) parts[(size_t)blockIdx.x * Op::NQ + j] = t;
+        }
+    }
+}
+
+// Column order of the nonzeros inside every tile (to_col), or back to row order.  In column
+// order the gathers of one wavefront walk the gathered vector in increasing address order,
+// so neighbouring lanes share cache lines; pos[p] keeps the row-order offset of the nonzero
+// stored at p, which k_pass uses to stage each product in its row-order slot.  Ties (one
+// column in several rows of the tile) keep row order.  One workgroup per item; other item
+// kinds keep row order.
+template <class M>
+__global__ __launch_bounds__(kWG) void k_tile_order(const int4 *__restrict__ items,
+                                                    int *__restrict__ ci, M *__restrict__ va,
+                                                    unsigned short *__restrict__ pos,
+                                                    int to_col) {
+    __shared__ unsigned long long key[kMaxTileNnz];
+    __shared__ M val[kMaxTileNnz];
+    const int4 it = items[blockIdx.x];
+    if ((it.w & 3) != IT_TILE) return;
+    const int P0 = it.y, cnt = (it.w >> 2) & 4095;
+    const int tid = threadIdx.x;
+    if (to_col) {
+        int N = 1;
+        while (N < cnt) N <<= 1;
+        for (int k = tid; k < N; k += kWG) {
+            key[k] = k < cnt ? ((unsigned long long)(unsigned)ci[P0 + k] << 12) | (unsigned)k
+                             : ~0ull;
+            if (k < cnt) val[k] = va[P0 + k];
+        }
+        __syncthreads();
+        for (int size = 2; size <= N; size <<= 1)  // bitonic sort of key[0, N)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = tid; i < N; i += kWG) {
+                    const int j = i ^ stride;
+                    if (j > i) {
+                        const bool up = (i & size) == 0;
+                        const unsigned long long a = key[i], b = key[j];
+                        if ((a > b) == up) {
+                            key[i] = b;
+                            key[j] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int q = tid; q < cnt; q += kWG) {
+            const int k = (int)(key[q] & 4095ull);
+            ci[P0 + q] = (int)(key[q] >> 12);
+            va[P0 + q] = val[k];
+            pos[P0 + q] = (unsigned short)k;
+        }
+    } else {
+        for (int q = tid; q < cnt; q += kWG) {
+            const int k = pos[P0 + q];
+            key[k] = (unsigned long long)(unsigned)ci[P0 + q];
+            val[k] = va[P0 + q];
+        }
+        __syncthreads();
+        for (int k = tid; k < cnt; k += kWG) {
+            ci[P0 + k] = (int)key[k];
+            va[P0 + k] = val[k];
         }
     }
 }
@@ -1051,9 +1122,14 @@ hipError_t run_pass(const DevMat &M, Op op, double *parts, hipStream_t st,
     using S = typename Op::Sum;
     // LDS: staged products (tile_nnz), row sums (tile_rows), row pointers (tile_rows + 1)
     const size_t lds = (size_t)(M.tile_nnz + M.tile_rows) * sizeof(S) + (M.tile_rows + 1) * sizeof(int);
-    if (M.n_items > 0)
-        hipLaunchKernelGGL(k_pass<Op>, dim3(M.n_items), dim3(kWG), lds, st, M.items, M.rp, op,
-                           reinterpret_cast<S *>(M.split_part), parts, M.tile_nnz, M.tile_rows);
+    if (M.n_items > 0 && M.sorted)
+        hipLaunchKernelGGL((k_pass<Op, true>), dim3(M.n_items), dim3(kWG), lds, st, M.items,
+                           M.rp, op, reinterpret_cast<S *>(M.split_part), parts, M.tile_nnz,
+                           M.tile_rows, M.pos);
+    else if (M.n_items > 0)
+        hipLaunchKernelGGL((k_pass<Op, false>), dim3(M.n_items), dim3(kWG), lds, st, M.items,
+                           M.rp, op, reinterpret_cast<S *>(M.split_part), parts, M.tile_nnz,
+                           M.tile_rows, nullptr);
     if (ev_mid) {
         hipError_t e = hipEventRecord(ev_mid, st);
         if (e != hipSuccess) return e;
@@ -1385,6 +1461,17 @@ hipError_t launch_disp_promote(const DispSet &v, long long n, long long m, hipSt
 hipError_t launch_anchor_out(double *out, const double *a, const float *d, double h,
                              const double *mul, const int *perm, long long n, hipStream_t st) {
     hipLaunchKernelGGL(k_anchor_out, grid_for(n), dim3(256), 0, st, out, a, d, h, mul, perm, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_order(const DevMat &M, bool mat_f32, bool to_col, hipStream_t st) {
+    if (!M.pos || M.n_items == 0) return hipSuccess;
+    if (mat_f32)
+        hipLaunchKernelGGL(k_tile_order<float>, dim3(M.n_items), dim3(kWG), 0, st, M.items, M.ci,
+                           static_cast<float *>(M.va), M.pos, to_col ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_tile_order<double>, dim3(M.n_items), dim3(kWG), 0, st, M.items,
+                           M.ci, static_cast<double *>(M.va), M.pos, to_col ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -95,7 +95,8 @@ int validate_options(const hprlp_options &o, std::string &err) {
               o.short_max >= 1 && o.short_max <= o.tile_nnz &&
               o.split_len >= o.short_max && o.chunk_nnz >= 256 && o.stall_ratio > 0 &&
               o.stall_ratio <= 1 && o.rho > 0 && o.rho <= 2 &&
-              (o.t1_zero == 0 || o.t1_zero == 1) && (o.setup_on_host == 0 || o.setup_on_host == 1);
+              (o.t1_zero == 0 || o.t1_zero == 1) && (o.setup_on_host == 0 || o.setup_on_host == 1) &&
+              o.tile_order >= -1 && o.tile_order <= 1 && !(o.t1_zero && o.tile_order == 1);
     if (!ok) err = "invalid option value";
     return ok ? HPRLP_OK : HPRLP_EINVAL;
 }

@@ -298,3 +298,27 @@ def test_create_rejects_a_workspace_sized_for_host_preprocessing(lib):
                           C.byref(o), C.c_void_p(256), small, None)
     msg = lib.hprlp_last_error(None).decode()
     assert rc == hprlp.EINVAL and "workspace too small" in msg and str(need) in msg, msg
+
+
+def test_tile_order_option(lib):
+    # 0 (default, row order), 1 and -1 (the autotuner decides) are the values; column order
+    # needs the row-order slot of every nonzero in the workspace (2 bytes per nonzero per
+    # matrix) when it may be used, and is refused with T1 = 0, whose kernels read A row by row
+    assert hprlp.default_options().tile_order == 0
+    nnz = 10**6
+    base = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options(tile_order=0))
+    forced = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options(tile_order=1))
+    tuned = hprlp.workspace_bytes(5000, 5000, 20000, nnz,
+                                  hprlp.default_options(tile_order=-1, autotune=1))
+    untuned = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options(tile_order=-1))
+    assert forced - base >= 4 * nnz and untuned == base
+    assert tuned - hprlp.workspace_bytes(5000, 5000, 20000, nnz,
+                                         hprlp.default_options(tile_order=0, autotune=1)) >= 4 * nnz
+    for bad in (dict(tile_order=2), dict(tile_order=-2), dict(tile_order=1, t1_zero=1)):
+        with pytest.raises(hprlp.HPRLPError) as e:
+            hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(**bad))
+        assert e.value.code == hprlp.EINVAL, bad
+    # T1 = 0 with -1: row order, no slots
+    t1 = hprlp.default_options(t1_zero=1, autotune=1, tile_order=-1)
+    assert hprlp.workspace_bytes(100, 0, 400, 2000, t1) == hprlp.workspace_bytes(
+        100, 0, 400, 2000, hprlp.default_options(t1_zero=1, autotune=1, tile_order=0))
