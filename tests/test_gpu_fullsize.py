@@ -14,7 +14,7 @@ Both sides use lambda = 1 there: after the Pock-Chambolle pass lambda_1(A~ A~^T)
 by the oracle tests), so 1 is a valid lambda of the method.  The power method itself is
 compared at full size on a fixed count of 50 iterations (power_tol = 0).  The
 mixed-precision workloads are checked on their FP64-phase kernels (FP32 A, FP64 vectors),
-which give FP64 iterates.
+which give FP64 iterates, and on their FP32 phase against an FP32 rounding bound.
 """
 import numpy as np
 import pytest
@@ -81,6 +81,30 @@ def test_fullsize_transport10m_fp64_phase_kernels():
 
 def test_fullsize_zipf4m_fp64_phase_kernels():
     _single("zipf4m", 30, hprlp.FP64_A32)
+
+
+# FP32 phase of MIXED (displacements from the FP64 anchor) at full size: within the FP32
+# rounding bound of tests/test_gpu_precision.py (two roundings per iteration of one outer
+# loop, at most 50 iterations here: 2 * 50 * 2^-24 ~ 6e-6) of the FP64 oracle.
+@pytest.mark.parametrize("name,iters", [("transport10m", 100), ("zipf4m", 30)])
+def test_fullsize_mixed_fp32_phase(name, iters):
+    lp = lpgen.make(name)
+    ref = oracle.solve(lp, max_iter=iters, lambda_override=1.0, check_every=CE, tol=1e-30)
+    s = hprlp.Solver(lp, max_iter=iters, lambda_override=1.0, autotune=1, tol=1e-30,
+                     precision=hprlp.MIXED, tol_switch=1e-30, check_every=CE)
+    sol = s.solve()
+    assert sol.stats["iters"] == ref.iters == iters and sol.stats["iters_fp32"] == iters
+    bound = 2 * CE * 2.0 ** -24
+    pairs = dict(x_bar=(sol.x, ref.x), y_bar=(sol.y, ref.y), z_bar=(sol.z, ref.z),
+                 x_cur=(s.iterate(hprlp.XCUR), ref.x_cur),
+                 y_cur=(s.iterate(hprlp.YCUR), ref.y_cur))
+    out = {k: rel(a, b) for k, (a, b) in pairs.items()}
+    print(name, "mixed FP32 phase", {k: f"{v:.2e}" for k, v in out.items()})
+    for k, v in out.items():
+        assert v <= bound, (name, k, v)
+    tr = s.trace()
+    np.testing.assert_array_equal(tr[:, 0], ref.trace[:, 0])
+    s.close()
 
 
 def test_fullsize_batch256_sampled_instances():
