@@ -122,7 +122,8 @@ typedef struct {
     int t1_zero;             /* 1: the T1 = 0 variant of Section 3.2 for LPs without        */
                              /* inequality rows (m2 = 0): the y-step solves with A A^T      */
                              /* exactly (eq. AATy=R) through a dense inverse of A~A~^T      */
-                             /* formed at create (m <= 8192, A of full row rank, FP64,      */
+                             /* formed at create (m <= 65536, 8 m^2 bytes of workspace,     */
+                             /* A of full row rank, FP64,                                    */
                              /* single LPs; EINVAL / EDIM otherwise), sigma by eq.          */
                              /* sigma_T1=0; no power method.  0 (default): T1 = lambda I -  */
                              /* A A^T                                                        */

@@ -70,8 +70,9 @@ constexpr int kTuneReps = 10;
 
 // T1 = 0 variant: dense inverse of A~A~^T and its scratch.
 struct T1Dev {
-    double *F = nullptr, *LT = nullptr, *G = nullptr;  // [m][m] each
-    double *r = nullptr, *d0 = nullptr, *dd = nullptr; // [m]
+    double *G = nullptr;                               // [mp][mp], mp = t1_padded_rows(m)
+    double *U = nullptr, *V = nullptr, *S = nullptr;   // [mp][64], [mp][64], [64][64]
+    double *r = nullptr, *d0 = nullptr, *dd = nullptr; // [m], [m], [mp]
     double *parts = nullptr;                           // [t1_parts_len()]
 };
 
@@ -293,9 +294,10 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     }
     T1Dev t1;
     if (p.t1m > 0) {
-        const size_t mm = (size_t)p.t1m * (size_t)p.t1m;
-        t1.F = cv.arr<double>(mm); t1.LT = cv.arr<double>(mm); t1.G = cv.arr<double>(mm);
-        t1.r = cv.arr<double>(m); t1.d0 = cv.arr<double>(m); t1.dd = cv.arr<double>(m);
+        const size_t mp = (size_t)t1_padded_rows((int)p.t1m);
+        t1.G = cv.arr<double>(mp * mp);
+        t1.U = cv.arr<double>(mp * 64); t1.V = cv.arr<double>(mp * 64); t1.S = cv.arr<double>(64 * 64);
+        t1.r = cv.arr<double>(m); t1.d0 = cv.arr<double>(m); t1.dd = cv.arr<double>(mp);
         t1.parts = cv.arr<double>(t1_parts_len());
     }
     PrepScratch ps;
@@ -744,8 +746,8 @@ int t1_check(const hprlp_options &o, bool batched, int64_t m, int64_t m2, std::s
 // 1e-10 times its diagonal entry of A~A~^T).
 int t1_setup(hprlp_handle *h) {
     const int m = (int)h->m;
-    HIPCHK(h, t1_build_inverse(h->A, h->T, m, h->t1.F, h->t1.LT, h->t1.G, h->t1.d0, h->t1.dd,
-                               h->st));
+    HIPCHK(h, t1_build_inverse(h->A, h->T, m, h->t1.G, h->t1.U, h->t1.V, h->t1.S, h->t1.d0,
+                               h->t1.dd, h->st));
     std::vector<double> d0((size_t)m), dd((size_t)m);
     int rc;
     if ((rc = download(h, d0.data(), h->t1.d0, (size_t)m)) ||

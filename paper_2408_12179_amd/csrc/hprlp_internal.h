@@ -253,12 +253,16 @@ hipError_t prep_vectors(const PrepArgs &a, const int *row_off, const int *col_of
 // ---------------------------------------------------------------- T1 = 0 (t1zero.hip)
 // Section 3.2, item 1: LPs without inequality rows, y-step solved exactly through the
 // dense inverse G of A~A~^T (at most kT1MaxRows rows).
-constexpr int kT1MaxRows = 8192;  // k_gram / k_linv hold m doubles (64 KB) in LDS
+constexpr int kT1MaxRows = 65536;  // G takes 8 mp^2 bytes (34 GB at this bound)
 size_t t1_parts_len();
-// G = (A~A~^T)^{-1} via LDL^T; F, LT: m*m scratch; diag0 / diagd: the diagonal of A~A~^T
-// and the LDL^T pivots (for the rank check on the host)
-hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, double *LT,
-                            double *G, double *diag0, double *diagd, hipStream_t st);
+// rows of the padded dense arrays: m rounded up to the 64-wide panels
+int t1_padded_rows(int m);
+// G = (A~A~^T)^{-1} in place in F ([mp][mp], mp = t1_padded_rows(m); G's rows have stride
+// mp), by a blocked symmetric sweep; U, V: [mp][64] and Sb: [64][64] scratch; diag0 [m]: the
+// diagonal of A~A~^T; diagd [mp]: its LDL^T pivots (for the rank check on the host)
+hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, double *U,
+                            double *V, double *Sb, double *diag0, double *diagd,
+                            hipStream_t st);
 // y-step: r = b~ - A~ x_hat, then y_bar = y + (G r) / sigma and the y update of Algorithm 2
 hipError_t t1_row_step(const DevMat &A, const VecSet<double> &v, const IterScalars &s,
                        const double *G, double *r, int m, bool keep, hipStream_t st);

@@ -261,15 +261,17 @@ def test_device_setup_scratch_is_in_the_workspace(lib):
 
 def test_t1_zero_limits(lib):
     o = hprlp.default_options(t1_zero=1)
-    assert hprlp.workspace_bytes(100, 0, 400, 2000, o) > hprlp.workspace_bytes(
-        100, 0, 400, 2000, hprlp.default_options()) + 3 * 8 * 100 * 100 - 1
+    # G of 128 x 128 (m = 100 padded to the 64-wide panels) plus two 128 x 64 panels
+    assert hprlp.workspace_bytes(100, 0, 400, 2000, o) >= hprlp.workspace_bytes(
+        100, 0, 400, 2000, hprlp.default_options()) + 8 * (128 * 128 + 2 * 128 * 64)
     with pytest.raises(hprlp.HPRLPError) as e:
         hprlp.workspace_bytes(100, 5, 400, 2000, o)  # inequality rows
     assert e.value.code == hprlp.EINVAL
     with pytest.raises(hprlp.HPRLPError) as e:
-        hprlp.workspace_bytes(8193, 0, 40000, 200000, o)  # beyond the dense inverse
+        hprlp.workspace_bytes(65537, 0, 400000, 2000000, o)  # beyond the dense inverse
     assert e.value.code == hprlp.EDIM
-    assert hprlp.workspace_bytes(8192, 0, 40000, 200000, o) >= 3 * 8 * 8192 * 8192
+    assert hprlp.workspace_bytes(65536, 0, 400000, 2000000, o) >= 8 * 65536 * 65536
+    assert hprlp.workspace_bytes(8193, 0, 40000, 200000, o) >= 8 * 8256 * 8256
     with pytest.raises(hprlp.HPRLPError) as e:
         hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=1,
                                                                        precision=hprlp.MIXED))

@@ -211,11 +211,13 @@ def test_fullsize_ot4m_t1zero_first_y_step():
     s.close()
 
 
-def test_t1zero_at_the_row_limit():
-    """T1 = 0 near its row limit (OT 4096 x 4096: m = 8191, n = 16.8M): eq. AATy=R holds for
-    the first y-step, as in the ot4m test."""
+@pytest.mark.parametrize("N", [4096, 8192], ids=["m8191", "m16383"])
+def test_t1zero_large_m(N):
+    """T1 = 0 with many 64-wide panels of the blocked sweep and several 4096-column chunks of
+    the Gram kernel (OT N x N: m = 2N - 1; N = 8192 gives n = 67M, nnz = 134M, G = 2.1 GB):
+    eq. AATy=R holds for the first y-step, as in the ot4m test."""
     import scipy.sparse as sp
-    lp = lpgen.ot_lp(4096, 4096, seed=11)
+    lp = lpgen.ot_lp(N, N, seed=11)
     s = hprlp.Solver(lp, t1_zero=1, max_iter=1)
     sol = s.solve()
     dr, dc = s.iterate(hprlp.DROW), s.iterate(hprlp.DCOL)
@@ -225,5 +227,6 @@ def test_t1zero_at_the_row_limit():
     xb, yb = sol.x / (bb * dc), sol.y / (bc * dr)
     lhs = At @ (At.T @ yb)
     rhs = dr * lp.b / bb - 2.0 * (At @ xb)
-    assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs)
+    assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs), \
+        np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs)
     s.close()
