@@ -216,7 +216,7 @@ def run_batched(args):
     P = {"mixed": hprlp.MIXED, "fp64a32": hprlp.FP64_A32}.get(args.precision, hprlp.FP64)
     opts = dict(check_every=ce, tol=args.tol, time_limit=args.ttt_cap, precision=P,
                 profile=args.profile_every, autotune=0 if args.no_autotune else 1,
-                tile_order=args.tile_order)
+                tile_order=args.tile_order, bundle_rows=args.bundle_rows)
     t0 = time.perf_counter()
     solver = hprlp.Solver(lp, batched=True, **opts)
     t_create = time.perf_counter() - t0
@@ -376,7 +376,8 @@ def run_single(args):
     opts = dict(tol=args.tol, time_limit=args.time_limit, precision=P, check_every=150,
                 profile=50 if sampled else 0, autotune=0 if args.no_autotune else 1,
                 setup_on_host=1 if args.setup_on_host else 0,
-                t1_zero=1 if args.t1_zero else 0, tile_order=args.tile_order)
+                t1_zero=1 if args.t1_zero else 0, tile_order=args.tile_order,
+                bundle_rows=args.bundle_rows)
     if args.stall_checks is not None:
         opts["stall_checks"] = args.stall_checks
     t0 = time.perf_counter()
@@ -573,6 +574,8 @@ def main():
     ap.add_argument("--setup-on-host", action="store_true",
                     help="preprocess on the host instead of the GPU (bit-identical arrays)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bundle-rows", type=int, default=-1, choices=[-1, 0, 1],
+                    help="row bundles: -1 shift-structured runs of A (default), 0 none, 1 all")
     ap.add_argument("--tile-order", type=int, default=0, choices=[-1, 0, 1],
                     help="nonzeros inside tiles: 0 row order, 1 column order, -1 autotuner")
     ap.add_argument("--stall-checks", type=int, default=None,

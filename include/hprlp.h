@@ -140,6 +140,15 @@ typedef struct {
                              /* per nonzero); -1 = chosen per matrix by the autotuner (row  */
                              /* order when autotune = 0).  Not with t1_zero (EINVAL for 1;  */
                              /* -1 means row order there)                                    */
+    int bundle_rows;         /* row bundles: runs of >= 2 consecutive rows of equal length  */
+                             /* 256..16384 stored k-major in groups of up to 64, one lane   */
+                             /* per row, so where each row's columns are its predecessor's  */
+                             /* plus one (the demand rows of transportation and transport  */
+                             /* LPs) the gathers coalesce.  -1 (default): such runs of A    */
+                             /* (the row pass); 0: none; 1: every equal-length run of A and */
+                             /* A^T.  Sums keep a fixed order.  Not with t1_zero (EINVAL    */
+                             /* for 1; -1 means none there).  Adds a bounded share to       */
+                             /* hprlp_workspace_bytes when not 0                              */
 } hprlp_options;
 
 typedef struct {
@@ -327,8 +336,9 @@ int hprlp_get_trace_instance(const hprlp_handle *h, int32_t i, double *out, long
 
 /* Schedule in use for A (matrix = 0, the row pass) or A^T (matrix = 1, the column pass):
  * params[5] = {tile_nnz, tile_rows, short_max, split_len, chunk_nnz} (nullable),
- * counts[5] = {work items incl. padding, tiles, whole-workgroup rows, split chunks,
- * 1 if the tiles hold their nonzeros in column order (tile_order) else 0} (nullable), *tuned_ms = the autotuner's measured time of one pass launch with it (0 when
+ * counts[6] = {work items incl. padding, tiles, whole-workgroup rows, split chunks,
+ * 1 if the tiles hold their nonzeros in column order (tile_order) else 0, row-bundle work
+ * items (bundle_rows)} (nullable), *tuned_ms = the autotuner's measured time of one pass launch with it (0 when
  * the autotuner did not run; nullable).  Host only. */
 int hprlp_get_schedule(const hprlp_handle *h, int matrix, int32_t *params, int64_t *counts,
                        double *tuned_ms);

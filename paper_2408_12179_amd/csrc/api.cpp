@@ -118,6 +118,8 @@ struct hprlp_handle {
     bool noalloc = false;                   // created by hprlp_create_noalloc (static scratch)
     hipStream_t cap_st = nullptr;   // single LP: stream the chunk graphs are captured on
     DevMat A, T;
+    int *bund_ci = nullptr;         // staging copy of one bundle (create only)
+    void *bund_va = nullptr;
     VecSet<double> v64;
     VecSet<float> v32;
     DispSet vdisp;                          // MIXED FP32 phase: displacements (aliases v32)
@@ -197,7 +199,12 @@ struct Plan {
     bool prep = false;   // scratch of the device preprocessing
     int64_t t1m = 0;     // T1 = 0: rows of the dense inverse of A~A~^T (0: off)
     bool tile_pos = false;  // tiles may be stored in column order: row-order slots per nonzero
+    int64_t bundle_tmp = 0; // row bundles possible: entries of the row-major copy of one bundle
 };
+
+// Row bundles are possible (every mode but 0); never with T1 = 0, whose kernels read A row
+// by row.
+bool bundles_possible(const hprlp_options &o) { return !o.t1_zero && o.bundle_rows != 0; }
 
 // Column-ordered tiles are possible (forced, or left to the autotuner); never with T1 = 0,
 // whose kernels read A row by row.
@@ -300,6 +307,12 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         t1.r = cv.arr<double>(m); t1.d0 = cv.arr<double>(m); t1.dd = cv.arr<double>(mp);
         t1.parts = cv.arr<double>(t1_parts_len());
     }
+    int *bund_ci = nullptr;
+    void *bund_va = nullptr;
+    if (p.bundle_tmp > 0) {
+        bund_ci = cv.arr<int>((size_t)p.bundle_tmp);
+        bund_va = cv.take((size_t)p.bundle_tmp * vs);
+    }
     PrepScratch ps;
     if (p.prep) {  // last: nothing of the solve lives after it
         for (auto &b2 : ps.u) b2 = cv.arr<uint32_t>(nnz);
@@ -325,6 +338,8 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
     if (h) {
         h->prep = ps;
         h->t1 = t1;
+        h->bund_ci = bund_ci;
+        h->bund_va = bund_va;
         h->A.rp = A.rp; h->A.ci = A.ci; h->A.va = A.va; h->A.items = A.items;
         h->A.splits = A.splits; h->A.split_part = A.split_part; h->A.pos = A.pos;
         h->T.rp = T.rp; h->T.ci = T.ci; h->T.va = T.va; h->T.items = T.items;
@@ -374,6 +389,20 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n
     p.splitT = (int)std::min<int64_t>(n, nnz / split + 1);
     p.slotsA = (int)ch + p.splitA;
     p.slotsT = (int)ch + p.splitT;
+    if (bundles_possible(o)) {
+        // a bundle has >= 2 rows of >= kBundleMinLen nonzeros and ceil(L / kBundleK) items,
+        // each row one slot per item and one finisher: items <= nnz/128 + bundles + padding,
+        // slots <= nnz/64 + bundled rows, bundled rows <= nnz/kBundleMinLen
+        const int64_t brows = std::min<int64_t>(nnz / kBundleMinLen, std::max(m, n));
+        const int64_t bitems = nnz / (2 * kBundleK) + brows / 2 + kXCD;
+        p.itemsA = (int)std::min<int64_t>((int64_t)p.itemsA + bitems, INT32_MAX / 8);
+        p.itemsT = (int)std::min<int64_t>((int64_t)p.itemsT + bitems, INT32_MAX / 8);
+        p.splitA = (int)std::min<int64_t>((int64_t)p.splitA + brows, INT32_MAX / 8);
+        p.splitT = (int)std::min<int64_t>((int64_t)p.splitT + brows, INT32_MAX / 8);
+        p.slotsA = (int)std::min<int64_t>((int64_t)p.slotsA + nnz / kBundleK + brows, INT32_MAX / 8);
+        p.slotsT = (int)std::min<int64_t>((int64_t)p.slotsT + nnz / kBundleK + brows, INT32_MAX / 8);
+        p.bundle_tmp = std::min<int64_t>(nnz, (int64_t)kBundleRows * kBundleMaxLen);
+    }
     p.power_cap = power_cap(o);
     p.n_inst = n_inst;
     p.batched = batched;
@@ -414,10 +443,10 @@ void build_segments(const Schedule &s, int n_inst, std::vector<int> &ptr,
     std::vector<std::vector<int>> per(n_inst);
     for (size_t p = 0; p < s.items.size(); ++p) {
         const int4 it = s.items[p];
-        const int kind = it.w & 3;
-        int inst = -1;
+        const int kind = it.w & kKindMask;
+        int inst = -1;  // BUNDLE and EMPTY items hold no check terms
         if (kind == IT_TILE || kind == IT_CHUNK) inst = it.z;
-        else if (kind == IT_ROW) inst = it.w >> 2;
+        else if (kind == IT_ROW) inst = it.w >> kKindBits;
         if (inst >= 0) per[inst].push_back((int)p);
     }
     for (size_t q = 0; q < s.splits.size(); ++q)
@@ -728,6 +757,32 @@ int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
                    const int32_t *inst_row, const int32_t *inst_col);
 int set_tile_order(hprlp_handle *h, bool row, bool col, bool to_col);
 
+// Store every bundle's nonzeros k-major (once, after the preprocessing): each bundle is
+// copied to the staging buffer, then written back in its new order.
+int store_bundles(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT) {
+    for (int w = 0; w < 2; ++w) {
+        DevMat &M = w ? h->T : h->A;
+        const int64_t *rp = w ? rpT : rpA;
+        const size_t vs = h->mixed ? sizeof(float) : sizeof(double);
+        for (const Bundle &b : M.bundles) {
+            const long long P0 = rp[b.r0];
+            const int L = (int)(rp[b.r0 + 1] - rp[b.r0]);
+            if (rp[b.r0 + b.R] - P0 != (int64_t)b.R * L || L < kBundleMinLen || L > kBundleMaxLen)
+                return fail(h, HPRLP_EHIP, "row bundle " + std::to_string(b.r0) +
+                                               ": rows of unequal length (internal error)");
+            const size_t cnt = (size_t)b.R * (size_t)L;
+            HIPCHK(h, hipMemcpyAsync(h->bund_ci, M.ci + P0, cnt * sizeof(int),
+                                     hipMemcpyDeviceToDevice, h->st));
+            HIPCHK(h, hipMemcpyAsync(h->bund_va, static_cast<char *>(M.va) + P0 * vs, cnt * vs,
+                                     hipMemcpyDeviceToDevice, h->st));
+            HIPCHK(h, launch_bundle_order(M.ci, M.va, h->mixed, h->bund_ci, h->bund_va, P0, b.R,
+                                          L, h->st));
+        }
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return HPRLP_OK;
+}
+
 // Where the T1 = 0 variant applies: one LP, equality rows only, FP64, a dense inverse of
 // A~A~^T of at most kT1MaxRows rows.
 int t1_check(const hprlp_options &o, bool batched, int64_t m, int64_t m2, std::string &err) {
@@ -823,8 +878,8 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
     const int32_t *irow = L.batched ? inst_row.data() : nullptr;
     const int32_t *icol = L.batched ? inst_col.data() : nullptr;
     auto build_schedules = [&](const int64_t *rpT) {
-        build_schedule(m, rowptr, spar, irow, h->A.host);
-        build_schedule(n, rpT, spar, icol, h->T.host);
+        build_schedule(m, rowptr, spar, irow, h->A.bundles, h->A.host);
+        build_schedule(n, rpT, spar, icol, h->T.bundles, h->T.host);
         for (DevMat *M : {&h->A, &h->T}) {
             M->n_items = (int)M->host.items.size();
             M->n_split = (int)M->host.splits.size();
@@ -863,6 +918,18 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
         }
         return HPRLP_OK;
     };
+    // Row bundles, fixed for the handle's lifetime: found on the caller's arrays (rows keep
+    // their order; A^T's rows are the columns after the renumbering by decreasing count)
+    if (bundles_possible(o)) {
+        find_bundles(m, rowptr, o.bundle_rows == 1 ? nullptr : colidx, irow, h->A.bundles);
+        if (o.bundle_rows == 1) {
+            std::vector<int64_t> deg((size_t)n, 0), rpT((size_t)n + 1, 0);
+            for (int64_t p = 0; p < nnz; ++p) deg[colidx[p]]++;
+            if (o.reorder) std::stable_sort(deg.begin(), deg.end(), std::greater<int64_t>());
+            for (int64_t j = 0; j < n; ++j) rpT[j + 1] = rpT[j] + deg[j];
+            find_bundles(n, rpT.data(), nullptr, icol, h->T.bundles);
+        }
+    }
     Plan need = bound_plan(m, n, nnz, o, L.n_inst, L.batched);
     std::vector<int64_t> rpt;
     std::vector<std::array<double, 8>> cst;
@@ -964,6 +1031,7 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
         h->bsnorm = cst[0][4];
         h->csnorm = cst[0][5];
     }
+    if (!rc) rc = store_bundles(h, rowptr, rpt.data());
     if (!rc && o.t1_zero) rc = t1_setup(h);
     h->t_prep_ms = now_ms() - t_prep;
     const double t_tune = now_ms();
@@ -1054,6 +1122,7 @@ extern "C" void hprlp_default_options(hprlp_options *o) {
     o->graph = 1;
     o->rho = 2.0;
     o->tile_order = 0;
+    o->bundle_rows = -1;
     resolve_options(*o);
 }
 
@@ -1593,7 +1662,7 @@ int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
                 for (size_t c; (c = next.fetch_add(1)) < cands.size();) {
                     const ScheduleParams &p = cands[c];
                     if (p.short_max > p.tile_nnz || p.split_len < p.short_max) continue;
-                    build_schedule(rows, rp, p, inst, built[c]);
+                    build_schedule(rows, rp, p, inst, (col ? h->T : h->A).bundles, built[c]);
                     ok[c] = 1;
                 }
             };
@@ -1956,8 +2025,10 @@ int set_schedules(hprlp_handle *h, const std::vector<int> &keep) {
             if (keep[b]) nnz += h->inst_nnz[b];
     }
     Schedule sa, stt;
-    build_schedule(h->m, h->rpA.data(), h->spA, keep.empty() ? h->inst_row.data() : ir.data(), sa);
-    build_schedule(h->n, h->rpT.data(), h->spT, keep.empty() ? h->inst_col.data() : ic.data(), stt);
+    build_schedule(h->m, h->rpA.data(), h->spA, keep.empty() ? h->inst_row.data() : ir.data(),
+                   h->A.bundles, sa);
+    build_schedule(h->n, h->rpT.data(), h->spT, keep.empty() ? h->inst_col.data() : ic.data(),
+                   h->T.bundles, stt);
     if ((int)sa.items.size() > h->capA[0] || (int)sa.splits.size() > h->capA[1] ||
         sa.n_chunk_slots > h->capA[2] || (int)stt.items.size() > h->capT[0] ||
         (int)stt.splits.size() > h->capT[1] || stt.n_chunk_slots > h->capT[2])
@@ -2459,6 +2530,7 @@ extern "C" int hprlp_get_schedule(const hprlp_handle *hc, int matrix, int32_t *p
         counts[0] = (int64_t)S.items.size(); counts[1] = S.n_tiles; counts[2] = S.n_rowitems;
         counts[3] = S.n_chunks;
         counts[4] = (matrix == 0 ? h->A : h->T).sorted ? 1 : 0;
+        counts[5] = S.n_bundle_items;
     }
     if (tuned_ms) *tuned_ms = h->tuned_ms[matrix];
     return HPRLP_OK;

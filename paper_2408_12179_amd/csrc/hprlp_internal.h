@@ -15,17 +15,34 @@ namespace hprlp {
 constexpr int kWG = 256;          // threads per workgroup of the SpMV passes (4 wavefronts)
 constexpr int kNQ = 6;            // check quantities per pass (row pass and column pass)
 
-// Work-item kinds of a pass schedule.  One workgroup processes one item.
-enum ItemKind : int { IT_TILE = 0, IT_ROW = 1, IT_CHUNK = 2, IT_EMPTY = 3 };
+// Work-item kinds of a pass schedule.  One workgroup processes one item; the kind is in
+// the low kKindBits bits of the item's w.
+enum ItemKind : int { IT_TILE = 0, IT_ROW = 1, IT_CHUNK = 2, IT_EMPTY = 3, IT_BUNDLE = 4 };
+constexpr int kKindBits = 3;
+constexpr int kKindMask = 7;
+// Row bundles: runs of up to 64 consecutive rows of equal length L (kBundleMinLen <= L <=
+// kBundleMaxLen) whose nonzeros are stored k-major (entry k of the bundle's row l at
+// P0 + k R + l, P0 = the first row's offset, R rows), so one lane per row reads the stream
+// and, where neighbouring rows hold neighbouring columns, the gathered vector coalesced.
+constexpr int kBundleRows = 64;
+constexpr int kBundleK = 64;       // entries of every row per work item
+constexpr int kBundleMinLen = 256;
+constexpr int kBundleMaxLen = 16384;
+struct Bundle {
+    int r0, R;
+};
 constexpr int kXCD = 8;           // accelerator complex dies of an MI355X
 constexpr int kMaxTileNnz = 2048; // kWG threads x 8 nonzeros (kernels.hip, kEPT)
 constexpr int kMaxTileRows = 1024;// kWG threads x 4 rows (kernels.hip, kRPT)
 
-// Schedule of one CSR matrix (host side, then uploaded).  The kind is in the low 2 bits of w.
-//   TILE : {r0, P0, inst, nrows << 14 | cnt << 2 | IT_TILE}  rows [r0, r0+nrows), all short,
+// Schedule of one CSR matrix (host side, then uploaded).  The kind is in the low 3 bits of w.
+//   TILE : {r0, P0, inst, nrows << 15 | cnt << 3 | IT_TILE}  rows [r0, r0+nrows), all short,
 //          nonzeros [P0, P0+cnt) with cnt <= tile_nnz <= 2048, nrows <= tile_rows <= 1024
-//   ROW  : {r, P0, P1, inst << 2 | IT_ROW}     one long row, whole workgroup
-//   CHUNK: {p0, p1, inst, slot << 2 | IT_CHUNK} piece of a split row; partial -> split_part[slot]
+//   ROW  : {r, P0, P1, inst << 3 | IT_ROW}     one long row, whole workgroup
+//   CHUNK: {p0, p1, inst, slot << 3 | IT_CHUNK} piece of a split row; partial -> split_part[slot]
+//   BUNDLE: {r0, p, s, C << 17 | (kn-1) << 9 | (R-1) << 3 | IT_BUNDLE} entries [k0, k0+kn) of
+//          the R rows of a bundle (p = P0 + k0 R); row l's partial -> split_part[s + l C],
+//          C = the bundle's item count
 //   EMPTY: {0, 0, 0, IT_EMPTY}                 padding so each class starts on an XCD boundary
 // splits: {row, slot0, nslots, inst} finished (fixed-order sum + epilogue) by a second kernel.
 struct Schedule {
@@ -33,7 +50,7 @@ struct Schedule {
     std::vector<int4> splits;
     int n_chunk_slots = 0;
     int tile_nnz = 0, tile_rows = 0;
-    long long n_tiles = 0, n_rowitems = 0, n_chunks = 0;
+    long long n_tiles = 0, n_rowitems = 0, n_chunks = 0, n_bundle_items = 0;
 };
 
 struct ScheduleParams {
@@ -42,9 +59,18 @@ struct ScheduleParams {
 
 // inst_of_row (nullable): instance of every row; tiles never straddle instances, and rows
 // with a negative instance are left out of the schedule (batched solves drop the instances
-// that have stopped).
+// that have stopped).  bundles (sorted by r0, inside one instance each): their rows are
+// scheduled as BUNDLE items whatever sp says.
 void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &sp,
-                    const int32_t *inst_of_row /* nullable */, Schedule &out);
+                    const int32_t *inst_of_row /* nullable */,
+                    const std::vector<Bundle> &bundles, Schedule &out);
+// Bundles of the rows of a CSR matrix: every maximal run of >= 2 consecutive rows of one
+// instance with equal length in [kBundleMinLen, kBundleMaxLen], cut into pieces of at most
+// kBundleRows rows (a last piece of one row is left out).  With col (nullable), a run also
+// needs each row's columns to be its predecessor's plus one (checked at the first, middle
+// and last entry), the pattern whose gathers a bundle coalesces.
+void find_bundles(int64_t rows, const int64_t *rowptr, const int32_t *col /* nullable */,
+                  const int32_t *inst_of_row /* nullable */, std::vector<Bundle> &out);
 
 // A CSR matrix resident in the workspace.
 struct DevMat {
@@ -64,7 +90,13 @@ struct DevMat {
     // order now.  Whole-workgroup rows and split chunks always keep row order.
     unsigned short *pos = nullptr;
     bool sorted = false;
+    // row bundles (fixed at create; their nonzeros are stored k-major from then on)
+    std::vector<Bundle> bundles;
 };
+// Store the nonzeros [P0, P0 + R L) of one bundle k-major, from their row-major copy in
+// (tci, tva); values are float (mat_f32) or double.
+hipError_t launch_bundle_order(int *ci, void *va, bool mat_f32, const int *tci, const void *tva,
+                               long long P0, int R, int L, hipStream_t st);
 // Reorder the nonzeros of every tile of M to column order (to_col) or back to row order;
 // values are float (mat_f32) or double.
 hipError_t launch_tile_order(const DevMat &M, bool mat_f32, bool to_col, hipStream_t st);

@@ -27,6 +27,8 @@
 // belongs to one instance, and its scalars (sigma, lambda, the Halpern counter, the first
 // inequality row, whether it still iterates) come from per-instance device arrays, so a
 // whole chunk of iterations can be captured once in a hipGraph.
+#include <algorithm>
+
 #include "hprlp_internal.h"
 
 namespace hprlp {
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
     __shared__ S red[4];
     __shared__ double redq[4];
     const int4 it = items[blockIdx.x];
-    const int kind = it.w & 3;
+    const int kind = it.w & kKindMask;
     const int tid = threadIdx.x;
     double q[NQ];
 #pragma unroll
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
             S *prod = reinterpret_cast<S *>(smem);
             S *rsum = prod + tile_cap;
             int *rpl = reinterpret_cast<int *>(rsum + rows_cap);
-            const int nrows = it.w >> 14, cnt = (it.w >> 2) & 4095;
+            const int nrows = it.w >> 15, cnt = (it.w >> kKindBits) & 4095;
             const int r1 = r0 + nrows;
             Pre pre[kPRE];
             if constexpr (Op::PREFETCH) {
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
         }
     } else if (kind == IT_ROW) {
         const int r = it.x;
-        const PassCtx ctx = op.begin(it.w >> 2);
+        const PassCtx ctx = op.begin(it.w >> kKindBits);
         Pre pre{};
         if (Op::PREFETCH && tid == 0) pre = op.load(r);
         S s = row_sum(op, it.y, it.z, tid);
@@ -290,7 +292,32 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
         // is not finished)
         S s = row_sum(op, it.x, it.y, tid);
         s = block_sum(s, red);
-        if (tid == 0) split_part[it.w >> 2] = s;
+        if (tid == 0) split_part[it.w >> kKindBits] = s;
+    } else if (kind == IT_BUNDLE) {
+        // entries [k0, k0 + kn) of the R rows of a bundle, stored k-major from p = it.y:
+        // entry kk of row l at p + kk R + l.  Lane l takes row l; wavefront w sums the entries
+        // kk = w, w + 4, ... in increasing kk (kEPT loads in flight, out-of-range slots re-load
+        // a valid entry and add zero), and the four wavefronts' sums are added in order.
+        const int R = ((it.w >> kKindBits) & 63) + 1, kn = ((it.w >> 9) & 255) + 1;
+        const int C = it.w >> 17;
+        const int lane = tid & 63, wv = tid >> 6, l = min(lane, R - 1);
+        S s = szero<S>();
+        for (int k0 = wv; k0 < kn; k0 += 4 * kEPT) {
+            typename Op::Raw raw[kEPT];
+#pragma unroll
+            for (int u = 0; u < kEPT; ++u) raw[u] = op.raw(it.y + min(k0 + 4 * u, kn - 1) * R + l);
+            S v[kEPT];
+#pragma unroll
+            for (int u = 0; u < kEPT; ++u) v[u] = op.prod(raw[u]);
+#pragma unroll
+            for (int u = 0; u < kEPT; ++u) s = s + (k0 + 4 * u < kn ? v[u] : szero<S>());
+        }
+        S *bsum = reinterpret_cast<S *>(smem);  // [4][64]
+        bsum[wv * 64 + lane] = s;
+        __syncthreads();
+        if (wv == 0 && lane < R)
+            split_part[it.z + lane * C] =
+                ((bsum[lane] + bsum[64 + lane]) + bsum[128 + lane]) + bsum[192 + lane];
     }  // IT_EMPTY: padding item, only the (zero) check partials below
     if constexpr (Op::NQ > 0) {
 #pragma unroll
@@ -315,8 +342,8 @@ __global__ __launch_bounds__(kWG) void k_tile_order(const int4 *__restrict__ ite
     __shared__ unsigned long long key[kMaxTileNnz];
     __shared__ M val[kMaxTileNnz];
     const int4 it = items[blockIdx.x];
-    if ((it.w & 3) != IT_TILE) return;
-    const int P0 = it.y, cnt = (it.w >> 2) & 4095;
+    if ((it.w & kKindMask) != IT_TILE) return;
+    const int P0 = it.y, cnt = (it.w >> kKindBits) & 4095;
     const int tid = threadIdx.x;
     if (to_col) {
         int N = 1;
@@ -1120,8 +1147,11 @@ template <class Op>
 hipError_t run_pass(const DevMat &M, Op op, double *parts, hipStream_t st,
                     hipEvent_t ev_mid = nullptr) {
     using S = typename Op::Sum;
-    // LDS: staged products (tile_nnz), row sums (tile_rows), row pointers (tile_rows + 1)
-    const size_t lds = (size_t)(M.tile_nnz + M.tile_rows) * sizeof(S) + (M.tile_rows + 1) * sizeof(int);
+    // LDS: staged products (tile_nnz), row sums (tile_rows), row pointers (tile_rows + 1);
+    // at least the four wavefronts' row sums of a bundle item
+    const size_t lds = std::max((size_t)(M.tile_nnz + M.tile_rows) * sizeof(S) +
+                                    (M.tile_rows + 1) * sizeof(int),
+                                4 * 64 * sizeof(S));
     if (M.n_items > 0 && M.sorted)
         hipLaunchKernelGGL((k_pass<Op, true>), dim3(M.n_items), dim3(kWG), lds, st, M.items,
                            M.rp, op, reinterpret_cast<S *>(M.split_part), parts, M.tile_nnz,
@@ -1461,6 +1491,33 @@ hipError_t launch_disp_promote(const DispSet &v, long long n, long long m, hipSt
 hipError_t launch_anchor_out(double *out, const double *a, const float *d, double h,
                              const double *mul, const int *perm, long long n, hipStream_t st) {
     hipLaunchKernelGGL(k_anchor_out, grid_for(n), dim3(256), 0, st, out, a, d, h, mul, perm, n);
+    return hipGetLastError();
+}
+
+// Bundle storage: destination offset e = k R + l (entry k of row l) takes source l L + k.
+template <class M>
+__global__ void k_bundle_order(int *__restrict__ ci, M *__restrict__ va,
+                               const int *__restrict__ tci, const M *__restrict__ tva,
+                               long long P0, int R, int L) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)R * L) return;
+    const long long src = (e % R) * (long long)L + e / R;
+    ci[P0 + e] = tci[src];
+    va[P0 + e] = tva[src];
+}
+
+hipError_t launch_bundle_order(int *ci, void *va, bool mat_f32, const int *tci, const void *tva,
+                               long long P0, int R, int L, hipStream_t st) {
+    const long long n = (long long)R * L;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (mat_f32)
+        hipLaunchKernelGGL(k_bundle_order<float>, grid, dim3(256), 0, st, ci,
+                           static_cast<float *>(va), tci, static_cast<const float *>(tva), P0, R,
+                           L);
+    else
+        hipLaunchKernelGGL(k_bundle_order<double>, grid, dim3(256), 0, st, ci,
+                           static_cast<double *>(va), tci, static_cast<const double *>(tva), P0,
+                           R, L);
     return hipGetLastError();
 }
 

@@ -96,7 +96,8 @@ int validate_options(const hprlp_options &o, std::string &err) {
               o.split_len >= o.short_max && o.chunk_nnz >= 256 && o.stall_ratio > 0 &&
               o.stall_ratio <= 1 && o.rho > 0 && o.rho <= 2 &&
               (o.t1_zero == 0 || o.t1_zero == 1) && (o.setup_on_host == 0 || o.setup_on_host == 1) &&
-              o.tile_order >= -1 && o.tile_order <= 1 && !(o.t1_zero && o.tile_order == 1);
+              o.tile_order >= -1 && o.tile_order <= 1 && !(o.t1_zero && o.tile_order == 1) &&
+              o.bundle_rows >= -1 && o.bundle_rows <= 1 && !(o.t1_zero && o.bundle_rows == 1);
     if (!ok) err = "invalid option value";
     return ok ? HPRLP_OK : HPRLP_EINVAL;
 }
@@ -174,14 +175,38 @@ void precondition(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *co
     }
 }
 
+void find_bundles(int64_t rows, const int64_t *rowptr, const int32_t *col,
+                  const int32_t *inst_of_row, std::vector<Bundle> &out) {
+    out.clear();
+    auto len = [&](int64_t r) { return rowptr[r + 1] - rowptr[r]; };
+    auto inst = [&](int64_t r) { return inst_of_row ? inst_of_row[r] : 0; };
+    auto shifted = [&](int64_t a, int64_t b, int64_t L) {
+        for (int64_t k : {(int64_t)0, L / 2, L - 1})
+            if ((int64_t)col[rowptr[b] + k] != (int64_t)col[rowptr[a] + k] + 1) return false;
+        return true;
+    };
+    for (int64_t r = 0; r < rows;) {
+        const int64_t L = len(r);
+        int64_t e = r + 1;
+        if (L >= kBundleMinLen && L <= kBundleMaxLen && inst(r) >= 0)
+            while (e < rows && len(e) == L && inst(e) == inst(r) && (!col || shifted(e - 1, e, L)))
+                ++e;
+        for (int64_t b = r; e - b >= 2; b += kBundleRows)
+            out.push_back({(int)b, (int)std::min<int64_t>(kBundleRows, e - b)});
+        r = e;
+    }
+}
+
 void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &sp,
-                    const int32_t *inst_of_row, Schedule &out) {
+                    const int32_t *inst_of_row, const std::vector<Bundle> &bundles,
+                    Schedule &out) {
     out.items.clear();
     out.splits.clear();
     out.n_chunk_slots = 0;
     out.tile_nnz = sp.tile_nnz;
     out.tile_rows = sp.tile_rows;
-    std::vector<int4> tiles, longrows, chunks;
+    out.n_bundle_items = 0;
+    std::vector<int4> tiles, longrows, chunks, bitems;
     std::vector<std::pair<int64_t, int64_t>> longlen;  // (len, row) for ordering
     auto inst = [&](int64_t r) { return inst_of_row ? inst_of_row[r] : 0; };
     int64_t r0 = 0, tnnz = 0;
@@ -189,13 +214,34 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
         if (r1 > r0) {
             const int nrows = (int)(r1 - r0), cnt = (int)(rowptr[r1] - rowptr[r0]);
             tiles.push_back(make_int4((int)r0, (int)rowptr[r0], inst(r0),
-                                      (nrows << 14) | (cnt << 2) | IT_TILE));
+                                      (nrows << 15) | (cnt << kKindBits) | IT_TILE));
         }
         r0 = r1;
         tnnz = 0;
     };
+    size_t nb = 0;  // next bundle
     for (int64_t r = 0; r < rows; ++r) {
         const int64_t len = rowptr[r + 1] - rowptr[r];
+        if (nb < bundles.size() && bundles[nb].r0 == r) {
+            const Bundle bd = bundles[nb++];
+            close_tile(r);
+            r0 = r + bd.R;
+            if (inst(r) >= 0) {
+                const int C = (int)((len + kBundleK - 1) / kBundleK);
+                const int s0 = out.n_chunk_slots;
+                for (int c = 0; c < C; ++c) {
+                    const int kn = (int)std::min<int64_t>(kBundleK, len - (int64_t)c * kBundleK);
+                    bitems.push_back(make_int4((int)r, (int)(rowptr[r] + (int64_t)c * kBundleK * bd.R),
+                                               s0 + c, (C << 17) | ((kn - 1) << 9) |
+                                                           ((bd.R - 1) << kKindBits) | IT_BUNDLE));
+                }
+                for (int l = 0; l < bd.R; ++l)
+                    out.splits.push_back(make_int4((int)r + l, s0 + l * C, C, inst(r)));
+                out.n_chunk_slots += bd.R * C;
+            }
+            r += bd.R - 1;
+            continue;
+        }
         if (inst(r) < 0) {  // row of an instance left out of this schedule
             close_tile(r);
             r0 = r + 1;
@@ -214,7 +260,7 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
                     const int64_t p0 = rowptr[r] + (int64_t)c * sp.chunk_nnz;
                     const int64_t p1 = std::min(rowptr[r + 1], p0 + sp.chunk_nnz);
                     chunks.push_back(make_int4((int)p0, (int)p1, inst(r),
-                                               ((out.n_chunk_slots + c) << 2) | IT_CHUNK));
+                                               ((out.n_chunk_slots + c) << kKindBits) | IT_CHUNK));
                 }
                 out.n_chunk_slots += nch;
             }
@@ -229,7 +275,8 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
                         const std::pair<int64_t, int64_t> &b) { return a.first > b.first; });
     for (auto &lr : longlen)
         longrows.push_back(make_int4((int)lr.second, (int)rowptr[lr.second],
-                                     (int)rowptr[lr.second + 1], (inst(lr.second) << 2) | IT_ROW));
+                                     (int)rowptr[lr.second + 1],
+                                     (inst(lr.second) << kKindBits) | IT_ROW));
     // Heaviest work first so the tail of the launch is made of small tiles.  Each class is
     // padded to a multiple of kXCD and interleaved: workgroup b runs on XCD b % kXCD, so the
     // item at position kXCD*k + x of a class segment is item x*q + k of the class (q = padded
@@ -245,8 +292,11 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
     // list would give the first XCD all the heavy rows.  Runs of equal length that fill every
     // XCD many times over (e.g. the supply and the demand rows of a transportation LP) are
     // range-interleaved; the rest is dealt round-robin, which keeps the XCD shares equal.
-    out.items.reserve(chunks.size() + longrows.size() + tiles.size() + 4 * kXCD + longlen.size());
+    out.items.reserve(chunks.size() + bitems.size() + longrows.size() + tiles.size() + 5 * kXCD +
+                      longlen.size());
     append(chunks);
+    out.n_bundle_items = (long long)bitems.size();
+    append(bitems);
     for (size_t a = 0; a < longrows.size();) {
         size_t e = a;
         while (e < longrows.size() && longlen[e].first == longlen[a].first) ++e;

@@ -48,7 +48,8 @@ class Options(C.Structure):
                 ("chunk_nnz", C.c_int), ("reorder", C.c_int), ("profile", C.c_int),
                 ("verbose", C.c_int), ("autotune", C.c_int), ("stall_ratio", C.c_double),
                 ("graph", C.c_int), ("rho", C.c_double), ("t1_zero", C.c_int),
-                ("setup_on_host", C.c_int), ("tile_order", C.c_int)]
+                ("setup_on_host", C.c_int), ("tile_order", C.c_int),
+                ("bundle_rows", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -278,14 +279,15 @@ class Solver:
     def schedule(self, matrix: int) -> dict:
         """Schedule of A (matrix=0, row pass) or A^T (matrix=1, column pass)."""
         params = np.zeros(5, dtype=np.int32)
-        counts = np.zeros(5, dtype=np.int64)
+        counts = np.zeros(6, dtype=np.int64)
         ms = C.c_double()
         self._check(self._lib.hprlp_get_schedule(self._h, matrix, _ptr(params), _ptr(counts),
                                                  C.byref(ms)))
         keys = ("tile_nnz", "tile_rows", "short_max", "split_len", "chunk_nnz")
         d = {k: int(v) for k, v in zip(keys, params)}
         d.update(items=int(counts[0]), tiles=int(counts[1]), row_items=int(counts[2]),
-                 chunks=int(counts[3]), column_order=bool(counts[4]), tuned_ms=ms.value)
+                 chunks=int(counts[3]), column_order=bool(counts[4]),
+                 bundle_items=int(counts[5]), tuned_ms=ms.value)
         return d
 
     def begin(self) -> dict:

@@ -324,3 +324,22 @@ def test_tile_order_option(lib):
     t1 = hprlp.default_options(t1_zero=1, autotune=1, tile_order=-1)
     assert hprlp.workspace_bytes(100, 0, 400, 2000, t1) == hprlp.workspace_bytes(
         100, 0, 400, 2000, hprlp.default_options(t1_zero=1, autotune=1, tile_order=0))
+
+
+def test_bundle_rows_option(lib):
+    # -1 (default: shift-structured runs of A), 0 and 1 (every equal-length run of A and A^T)
+    # are the values; when bundles may be used, the workspace holds a bounded worst case of
+    # their work items, partial-sum slots and one bundle's staging copy; refused with T1 = 0
+    assert hprlp.default_options().bundle_rows == -1
+    nnz = 10**6
+    off = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options(bundle_rows=0))
+    auto = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options())
+    forced = hprlp.workspace_bytes(5000, 5000, 20000, nnz, hprlp.default_options(bundle_rows=1))
+    assert auto == forced and auto - off >= 12 * nnz
+    for bad in (dict(bundle_rows=2), dict(bundle_rows=-2), dict(bundle_rows=1, t1_zero=1)):
+        with pytest.raises(hprlp.HPRLPError) as e:
+            hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(**bad))
+        assert e.value.code == hprlp.EINVAL, bad
+    # T1 = 0 with -1: no bundles, no extra workspace
+    assert hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=1)) == \
+        hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=1, bundle_rows=0))
