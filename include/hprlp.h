@@ -146,9 +146,9 @@ typedef struct {
                              /* plus one (the demand rows of transportation and transport  */
                              /* LPs) the gathers coalesce.  -1 (default): such runs of A    */
                              /* (the row pass); 0: none; 1: every equal-length run of A and */
-                             /* A^T.  Sums keep a fixed order.  Not with t1_zero (EINVAL    */
-                             /* for 1; -1 means none there).  Adds a bounded share to       */
-                             /* hprlp_workspace_bytes when not 0                              */
+                             /* A^T.  Sums keep a fixed order.  With t1_zero: -1 (A only);  */
+                             /* 1 is EINVAL.  Adds a bounded share to hprlp_workspace_bytes */
+                             /* when not 0                                                   */
 } hprlp_options;
 
 typedef struct {

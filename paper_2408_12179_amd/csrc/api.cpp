@@ -202,9 +202,10 @@ struct Plan {
     int64_t bundle_tmp = 0; // row bundles possible: entries of the row-major copy of one bundle
 };
 
-// Row bundles are possible (every mode but 0); never with T1 = 0, whose kernels read A row
-// by row.
-bool bundles_possible(const hprlp_options &o) { return !o.t1_zero && o.bundle_rows != 0; }
+// Row bundles are possible (every mode but 0).  With T1 = 0 only A's (mode -1): the Gram
+// matrix is formed from the row-major A before the bundles are stored, and the check's
+// ||A~^T v||^2 reads A~^T row by row.
+bool bundles_possible(const hprlp_options &o) { return o.bundle_rows != 0; }
 
 // Column-ordered tiles are possible (forced, or left to the autotuner); never with T1 = 0,
 // whose kernels read A row by row.
@@ -1031,8 +1032,8 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
         h->bsnorm = cst[0][4];
         h->csnorm = cst[0][5];
     }
-    if (!rc) rc = store_bundles(h, rowptr, rpt.data());
     if (!rc && o.t1_zero) rc = t1_setup(h);
+    if (!rc) rc = store_bundles(h, rowptr, rpt.data());
     h->t_prep_ms = now_ms() - t_prep;
     const double t_tune = now_ms();
     if (!rc && o.autotune && nnz >= kTuneMinNnz)

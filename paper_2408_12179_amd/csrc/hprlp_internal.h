@@ -295,6 +295,9 @@ int t1_padded_rows(int m);
 hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, double *U,
                             double *V, double *Sb, double *diag0, double *diagd,
                             hipStream_t st);
+// r = b~ - A~ x_hat through the pass kernel and A's schedule (kernels.hip)
+hipError_t launch_t1_resid(const DevMat &A, const double *xhat, const double *bd, double *r,
+                           hipStream_t st);
 // y-step: r = b~ - A~ x_hat, then y_bar = y + (G r) / sigma and the y update of Algorithm 2
 hipError_t t1_row_step(const DevMat &A, const VecSet<double> &v, const IterScalars &s,
                        const double *G, double *r, int m, bool keep, hipStream_t st);

@@ -570,6 +570,32 @@ template <class M, class V, bool FOLD, bool KEEP, bool B> struct RowOp {
     }
 };
 
+// Residual of the T1 = 0 y-step (Section 3.2, item 1): r = b~ - A~ x_hat, the right-hand
+// side that the dense inverse of A~A~^T is applied to.
+struct T1ResidOp {
+    using Sum = double;
+    using Raw = RawT<double>;
+    static constexpr int NQ = 0;
+    static constexpr bool PREFETCH = true;
+    struct Pre {
+        double bd;
+    };
+    const int *__restrict__ ci;
+    const double *__restrict__ va;
+    const double *__restrict__ xg;
+    const double *__restrict__ bd;
+    double *__restrict__ r;
+    IterScalars s;
+    __device__ __forceinline__ PassCtx begin(int) const { return ctx_single(s, nullptr); }
+    __device__ __forceinline__ Raw raw(int p) const { return load_raw(ci, va, p); }
+    __device__ __forceinline__ Sum prod(const Raw &q) const { return q.a * xg[q.j]; }
+    __device__ __forceinline__ Pre load(int i) const { return Pre{bd[i]}; }
+    __device__ __forceinline__ void apply(int i, Sum s_, const Pre &p, const PassCtx &,
+                                          double *) const {
+        r[i] = p.bd - s_;
+    }
+};
+
 // ------------------------------------------------------------------ MIXED, FP32 phase
 //
 // The FP32 phase keeps the iterate as FP32 displacements from the FP64 anchor w^{r,0} of
@@ -1375,6 +1401,12 @@ hipError_t launch_col_pass(int prec, bool keep, const DevMat &T, const void *vs,
                 : col_pass<M, V, F, false, false>(T, v, s, st, ev, ba)))
     HPRLP_PREC_DISPATCH(COL_CALL);
 #undef COL_CALL
+}
+
+hipError_t launch_t1_resid(const DevMat &A, const double *xhat, const double *bd, double *r,
+                           hipStream_t st) {
+    T1ResidOp op{A.ci, static_cast<const double *>(A.va), xhat, bd, r, IterScalars{}};
+    return run_pass(A, op, nullptr, st);
 }
 
 hipError_t launch_row_pass(int prec, bool keep, const DevMat &A, const void *vs,

@@ -16,8 +16,9 @@
 //     rank-64 update A_IJ -= V_I A_{J,P}^T of every lower tile (FP64 MFMA), which also writes
 //     the panel's new row and column;
 //   * the swept matrix is -G: one pass negates it and fills the upper triangle.
-// Every iteration then costs one residual pass over A~ and one dense matrix-vector product
-// with G (m^2 FP64 reads, HBM-bound), with the y epilogue of Algorithm 2 fused into it.  The
+// Every iteration then costs one residual pass over A~ (the pass kernel with A's schedule,
+// row bundles included) and one dense matrix-vector product with G (m^2 FP64 reads,
+// HBM-bound), with the y epilogue of Algorithm 2 fused into it.  The
 // checks need ||A~^T v||^2 (M of eq. def:M with T1 = 0, and eq. sigma_T1=0), from one pass
 // over A~^T.
 #include <hip/hip_runtime.h>
@@ -283,22 +284,6 @@ __global__ __launch_bounds__(kT) void k_sweep_finish(double *__restrict__ F, int
     }
 }
 
-// r = b~ - A~ x_hat (one wavefront per row)
-__global__ __launch_bounds__(kT) void k_t1_resid(const int *__restrict__ rp,
-                                                 const int *__restrict__ ci,
-                                                 const double *__restrict__ va,
-                                                 const double *__restrict__ xh,
-                                                 const double *__restrict__ bd, int m,
-                                                 double *__restrict__ r) {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
-    if (i >= m) return;
-    double s = 0.0;
-    for (int p = rp[i] + lane; p < rp[i + 1]; p += 64) s += va[p] * xh[ci[p]];
-    s = wave_sum(s);
-    if (lane == 0) r[i] = bd[i] - s;
-}
-
 // y-step with T1 = 0 and the rest of Algorithm 2's y update, one wavefront per row:
 // y_bar = y + (G r)_i / sigma; relaxed point rho y_bar + (1 - rho) y; Halpern average.
 __global__ __launch_bounds__(kT) void k_t1_solve(const double *__restrict__ G,
@@ -412,8 +397,8 @@ hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, 
 hipError_t t1_row_step(const DevMat &A, const VecSet<double> &v, const IterScalars &s,
                        const double *G, double *r, int m, bool keep, hipStream_t st) {
     const int nb = (m + kT / 64 - 1) / (kT / 64);
-    hipLaunchKernelGGL(k_t1_resid, dim3(nb), dim3(kT), 0, st, A.rp, A.ci,
-                       static_cast<const double *>(A.va), v.xhat, v.bd, m, r);
+    hipError_t e = launch_t1_resid(A, v.xhat, v.bd, r, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_t1_solve, dim3(nb), dim3(kT), 0, st, G, r, m, t1_padded_rows(m), v.y,
                        v.y0, v.ybar,
                        v.dy, s, keep ? 1 : 0);

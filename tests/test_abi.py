@@ -340,6 +340,6 @@ def test_bundle_rows_option(lib):
         with pytest.raises(hprlp.HPRLPError) as e:
             hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(**bad))
         assert e.value.code == hprlp.EINVAL, bad
-    # T1 = 0 with -1: no bundles, no extra workspace
-    assert hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=1)) == \
-        hprlp.workspace_bytes(100, 0, 400, 2000, hprlp.default_options(t1_zero=1, bundle_rows=0))
+    # T1 = 0 with -1: bundles of A possible (the residual pass runs on the pass kernel)
+    assert hprlp.workspace_bytes(1000, 0, 4000, 20000, hprlp.default_options(t1_zero=1)) > \
+        hprlp.workspace_bytes(1000, 0, 4000, 20000, hprlp.default_options(t1_zero=1, bundle_rows=0))

@@ -105,10 +105,12 @@ def test_t1zero_deterministic():
 
 
 def test_t1zero_parity_ot_512():
-    """m = 1023: the dense inverse spans many 16- and 64-wide tiles with ragged edges."""
+    """m = 1023: 16 panels of the blocked sweep, the last one padded; the residual pass
+    runs the demand rows (511 of 512 nonzeros, columns shifted by one) as row bundles."""
     lp = lpgen.ot_lp(512, 512, seed=506)
     ref = oracle.solve(lp, t1_zero=1, max_iter=100)
     s = hprlp.Solver(lp, t1_zero=1, max_iter=100)
+    assert s.schedule(0)["bundle_items"] > 0
     sol = s.solve()
     assert sol.stats["iters"] == ref.iters == 100
     for k, a, b in (("x", sol.x, ref.x), ("y", sol.y, ref.y), ("z", sol.z, ref.z),
