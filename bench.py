@@ -405,8 +405,13 @@ def run_single(args):
     solved = all(s["status"] == "OPTIMAL" for s in stats)
     iters = int(st["iters"])
     s_val = 4 if prec in ("mixed", "fp64a32") else 8
-    s_vec = 4 if (prec == "mixed" and st["iters_fp32"] == iters) else 8
-    col_b, row_b = pass_bytes(lp.m, lp.n, lp.nnz, s_val, s_vec)
+    col_b, row_b = pass_bytes(lp.m, lp.n, lp.nnz, s_val, 8)
+    if prec == "mixed" and iters > 0:
+        # the timed launches sample every 50th iteration: a share iters_fp32 / iters of them
+        # runs the FP32 phase (4-byte vectors), the rest the FP64 phase (8-byte vectors)
+        f32 = st["iters_fp32"] / iters
+        c4, r4 = pass_bytes(lp.m, lp.n, lp.nnz, s_val, 4)
+        col_b, row_b = f32 * c4 + (1 - f32) * col_b, f32 * r4 + (1 - f32) * row_b
     out = {
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": value * 1e3, "higher_is_better": False,
@@ -440,13 +445,13 @@ def run_single(args):
         col_ms, row_ms = solver.time_passes(20)
         split_pi = None
         timing = "HIP events around 20 launches of each pass after the timed solve"
-        if prec == "mixed" and st["iters_fp32"] < iters:
-            s_vec = 8
+        if prec == "mixed":  # launched after the solve, in the phase it ended in
+            s_vec = 4 if st["iters_fp32"] == iters else 8
             col_b, row_b = pass_bytes(lp.m, lp.n, lp.nnz, s_val, s_vec)
     row_kernel = "k_pass<RowOp> (y-step over A)"
     if args.t1_zero:  # residual pass over A, then the dense product with G = (A A^T)^-1
         row_b += 8 * lp.m * lp.m
-        row_kernel = "k_t1_resid + k_t1_solve (T1 = 0 y-step: residual over A, G r)"
+        row_kernel = "k_pass<T1ResidOp> + k_t1_solve (T1 = 0 y-step: residual over A, G r)"
     col_gbs = col_b / (col_ms * 1e-3) / 1e9
     row_gbs = row_b / (row_ms * 1e-3) / 1e9
     dom = "col" if col_ms >= row_ms else "row"
