@@ -211,6 +211,52 @@ def test_fullsize_ot4m_t1zero_first_y_step():
     s.close()
 
 
+def identity_plus_sparse_lp(m, per_row, seed):
+    """Equality LP with A = [I_m | R], R an m x m random sparse matrix with per_row FP32-exact
+    N(0,1) entries per row: full row rank by construction and A A^T = I + R R^T with
+    eigenvalues >= 1, so the explicit inverse is accurate at any m."""
+    rng = np.random.default_rng(seed)
+    cols = np.sort(rng.choice(m, size=(m, per_row), replace=True), axis=1)
+    keep = np.ones_like(cols, dtype=bool)
+    keep[:, 1:] = cols[:, 1:] != cols[:, :-1]
+    lens = 1 + keep.sum(axis=1)
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    colidx = np.empty(rowptr[-1], dtype=np.int32)
+    val = np.empty(rowptr[-1])
+    starts = rowptr[:-1]
+    colidx[starts] = np.arange(m)
+    val[starts] = 1.0
+    rest = np.ones(rowptr[-1], dtype=bool)
+    rest[starts] = False
+    colidx[rest] = (m + cols[keep]).astype(np.int32)
+    val[rest] = rng.standard_normal(int(keep.sum())).astype(np.float32).astype(np.float64)
+    n = 2 * m
+    b = rng.standard_normal(m).astype(np.float32).astype(np.float64)
+    c = rng.uniform(1.0, 2.0, n)
+    return lpgen.LP(f"ipr{m}", m, 0, n, rowptr, colidx, val, b, c, np.zeros(n),
+                    np.full(n, 10.0))
+
+
+@pytest.mark.parametrize("m", [32768])
+def test_t1zero_m32768(m):
+    """T1 = 0 at a quarter of its row bound beyond the OT sizes (512 panels of the blocked
+    sweep, 8 Gram chunks, G = 8.6 GB): eq. AATy=R holds for the first y-step."""
+    import scipy.sparse as sp
+    lp = identity_plus_sparse_lp(m, 8, seed=12)
+    s = hprlp.Solver(lp, t1_zero=1, max_iter=1)
+    sol = s.solve()
+    dr, dc = s.iterate(hprlp.DROW), s.iterate(hprlp.DCOL)
+    bb, bc = sol.stats["beta_b"], sol.stats["beta_c"]
+    A = sp.csr_matrix((lp.val, lp.colidx, lp.rowptr), shape=(lp.m, lp.n))
+    At = sp.diags(dr) @ A @ sp.diags(dc)
+    xb, yb = sol.x / (bb * dc), sol.y / (bc * dr)
+    lhs = At @ (At.T @ yb)
+    rhs = dr * lp.b / bb - 2.0 * (At @ xb)
+    assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs), \
+        np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs)
+    s.close()
+
+
 @pytest.mark.parametrize("N", [4096, 8192], ids=["m8191", "m16383"])
 def test_t1zero_large_m(N):
     """T1 = 0 with many 64-wide panels of the blocked sweep and several 4096-column chunks of
