@@ -3,7 +3,8 @@ oracle: the iterates after 100 iterations at the 1e-10 bar (norm-wise and entry 
 on the LPs where the default finds them (the demand rows of transportation and transport
 LPs, whose columns shift by one from row to row) and with every equal-length run of A and
 A^T bundled (dense LPs), in the three precisions, under a stress schedule, in a compacting
-batch, full solves, and bitwise reproducibility."""
+batch, at the edges of the bundle rules (minimum row length and bundle size, a run one row
+longer than a bundle, inequality rows), full solves, and bitwise reproducibility."""
 import numpy as np
 import pytest
 
@@ -153,3 +154,43 @@ def test_bundles_deterministic():
     b = hprlp.Solver(lp, max_iter=500, bundle_rows=1).solve()
     for u, v in ((a.x, b.x), (a.y, b.y), (a.z, b.z)):
         assert np.array_equal(u.view(np.uint64), v.view(np.uint64))
+
+
+def edge_lp(seed=620):
+    """Shifted runs at the edges of the bundle rules: 65 equality rows of exactly 256
+    nonzeros (one bundle of 64, the 65th row left to a tile), 2 equality rows of 300 (the
+    smallest bundle), 40 random short equality rows, then 70 shifted inequality rows of 257
+    (Pi_+ in the bundle finisher); columns boxed in [0, 10]."""
+    rng = np.random.default_rng(seed)
+    n = 40000
+    rows = []
+    rows += [r + 70 * np.arange(256) for r in range(65)]
+    rows += [20000 + r + 60 * np.arange(300) for r in range(2)]
+    rows += [np.sort(rng.choice(n, size=rng.integers(5, 30), replace=False)) for _ in range(40)]
+    m1 = len(rows)
+    rows += [100 + r + 150 * np.arange(257) for r in range(70)]
+    rowptr = np.concatenate([[0], np.cumsum([len(c) for c in rows])]).astype(np.int64)
+    colidx = np.concatenate(rows).astype(np.int32)
+    val = rng.standard_normal(len(colidx)).astype(np.float32).astype(np.float64)
+    m = len(rows)
+    x0 = rng.uniform(0.0, 10.0, n)
+    A = np.zeros(m)
+    for i in range(m):
+        A[i] = val[rowptr[i]:rowptr[i + 1]] @ x0[colidx[rowptr[i]:rowptr[i + 1]]]
+    b = A.copy()
+    b[m1:] -= 1.0
+    c = rng.standard_normal(n)
+    return lpgen.LP("bundle_edges", m1, m - m1, n, rowptr, colidx, val, b, c, np.zeros(n),
+                    np.full(n, 10.0))
+
+
+@pytest.mark.parametrize("sched", ["default", "stress"])
+def test_bundle_edges(sched):
+    lp = edge_lp()
+    ref = oracle.solve(lp, max_iter=100)
+    extra = STRESS if sched == "stress" else {}
+    s = hprlp.Solver(lp, max_iter=100, lambda_override=ref.lam, **extra)
+    # 64 rows x 4 items (256 = 4 * 64), 2 rows x 5 items (300), 64 + 6 rows x 5 items (257)
+    assert s.schedule(0)["bundle_items"] == 4 + 5 + 5 + 5, s.schedule(0)
+    check(iterates(s, s.solve(), ref))
+    s.close()
