@@ -141,12 +141,13 @@ typedef struct {
                              /* order when autotune = 0).  Not with t1_zero (EINVAL for 1;  */
                              /* -1 means row order there)                                    */
     int bundle_rows;         /* row bundles: runs of >= 2 consecutive rows of equal length  */
-                             /* 256..16384 stored k-major in groups of up to 64, one lane   */
+                             /* (<= 16384) stored k-major in groups of up to 64, one lane   */
                              /* per row, so where each row's columns are its predecessor's  */
-                             /* plus one (the demand rows of transportation and transport  */
-                             /* LPs) the gathers coalesce.  -1 (default): such runs of A    */
-                             /* (the row pass); 0: none; 1: every equal-length run of A and */
-                             /* A^T.  Sums keep a fixed order.  With t1_zero: -1 (A only);  */
+                             /* plus one (demand rows of transportation and transport LPs,  */
+                             /* QAP rows) the gathers coalesce.  -1 (default): such runs of */
+                             /* A of length >= 16 (the row pass); 0: none; 1: every         */
+                             /* equal-length run of A and A^T of length >= 256.  Sums keep  */
+                             /* a fixed order.  With t1_zero: -1 (A only);  */
                              /* 1 is EINVAL.  Adds a bounded share to hprlp_workspace_bytes */
                              /* when not 0                                                   */
 } hprlp_options;

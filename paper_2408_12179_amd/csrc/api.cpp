@@ -391,11 +391,12 @@ Plan bound_plan(int64_t m, int64_t n, int64_t nnz, const hprlp_options &o, int n
     p.slotsA = (int)ch + p.splitA;
     p.slotsT = (int)ch + p.splitT;
     if (bundles_possible(o)) {
-        // a bundle has >= 2 rows of >= kBundleMinLen nonzeros and ceil(L / kBundleK) items,
-        // each row one slot per item and one finisher: items <= nnz/128 + bundles + padding,
-        // slots <= nnz/64 + bundled rows, bundled rows <= nnz/kBundleMinLen
-        const int64_t brows = std::min<int64_t>(nnz / kBundleMinLen, std::max(m, n));
-        const int64_t bitems = nnz / (2 * kBundleK) + brows / 2 + kXCD;
+        // a bundle has >= 2 rows of >= kBundleMinShifted nonzeros and ceil(L / kBundleK)
+        // items: items <= nnz/128 + bundles + padding, bundles <= nnz/(2 kBundleMinShifted).
+        // Only bundles of more than kBundleK nonzeros per row use slots (one per row and item)
+        // and finishers (one per row): slots <= nnz/64 + such rows <= nnz/64 + nnz/kBundleK
+        const int64_t brows = std::min<int64_t>(nnz / kBundleK, std::max(m, n));
+        const int64_t bitems = nnz / (2 * kBundleK) + nnz / (2 * kBundleMinShifted) + kXCD;
         p.itemsA = (int)std::min<int64_t>((int64_t)p.itemsA + bitems, INT32_MAX / 8);
         p.itemsT = (int)std::min<int64_t>((int64_t)p.itemsT + bitems, INT32_MAX / 8);
         p.splitA = (int)std::min<int64_t>((int64_t)p.splitA + brows, INT32_MAX / 8);
@@ -445,9 +446,10 @@ void build_segments(const Schedule &s, int n_inst, std::vector<int> &ptr,
     for (size_t p = 0; p < s.items.size(); ++p) {
         const int4 it = s.items[p];
         const int kind = it.w & kKindMask;
-        int inst = -1;  // BUNDLE and EMPTY items hold no check terms
+        int inst = -1;  // EMPTY items and split BUNDLE items hold no check terms
         if (kind == IT_TILE || kind == IT_CHUNK) inst = it.z;
         else if (kind == IT_ROW) inst = it.w >> kKindBits;
+        else if (kind == IT_BUNDLE && (it.w >> 17) == 1) inst = it.z;
         if (inst >= 0) per[inst].push_back((int)p);
     }
     for (size_t q = 0; q < s.splits.size(); ++q)
@@ -768,7 +770,7 @@ int store_bundles(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT) {
         for (const Bundle &b : M.bundles) {
             const long long P0 = rp[b.r0];
             const int L = (int)(rp[b.r0 + 1] - rp[b.r0]);
-            if (rp[b.r0 + b.R] - P0 != (int64_t)b.R * L || L < kBundleMinLen || L > kBundleMaxLen)
+            if (rp[b.r0 + b.R] - P0 != (int64_t)b.R * L || L < kBundleMinShifted || L > kBundleMaxLen)
                 return fail(h, HPRLP_EHIP, "row bundle " + std::to_string(b.r0) +
                                                ": rows of unequal length (internal error)");
             const size_t cnt = (size_t)b.R * (size_t)L;

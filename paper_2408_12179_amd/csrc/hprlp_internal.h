@@ -20,13 +20,16 @@ constexpr int kNQ = 6;            // check quantities per pass (row pass and col
 enum ItemKind : int { IT_TILE = 0, IT_ROW = 1, IT_CHUNK = 2, IT_EMPTY = 3, IT_BUNDLE = 4 };
 constexpr int kKindBits = 3;
 constexpr int kKindMask = 7;
-// Row bundles: runs of up to 64 consecutive rows of equal length L (kBundleMinLen <= L <=
-// kBundleMaxLen) whose nonzeros are stored k-major (entry k of the bundle's row l at
-// P0 + k R + l, P0 = the first row's offset, R rows), so one lane per row reads the stream
-// and, where neighbouring rows hold neighbouring columns, the gathered vector coalesced.
+// Row bundles: runs of up to 64 consecutive rows of equal length L (L <= kBundleMaxLen; at
+// least kBundleMinShifted where each row's columns are its predecessor's plus one, at least
+// kBundleMinLen otherwise) whose nonzeros are stored k-major (entry k of the bundle's row l
+// at P0 + k R + l, P0 = the first row's offset, R rows), so one lane per row reads the
+// stream and, where neighbouring rows hold neighbouring columns, the gathered vector
+// coalesced.
 constexpr int kBundleRows = 64;
 constexpr int kBundleK = 64;       // entries of every row per work item
 constexpr int kBundleMinLen = 256;
+constexpr int kBundleMinShifted = 16;
 constexpr int kBundleMaxLen = 16384;
 struct Bundle {
     int r0, R;
@@ -42,7 +45,8 @@ constexpr int kMaxTileRows = 1024;// kWG threads x 4 rows (kernels.hip, kRPT)
 //   CHUNK: {p0, p1, inst, slot << 3 | IT_CHUNK} piece of a split row; partial -> split_part[slot]
 //   BUNDLE: {r0, p, s, C << 17 | (kn-1) << 9 | (R-1) << 3 | IT_BUNDLE} entries [k0, k0+kn) of
 //          the R rows of a bundle (p = P0 + k0 R); row l's partial -> split_part[s + l C],
-//          C = the bundle's item count
+//          C = the bundle's item count.  C = 1 (L <= kBundleK): the item applies the epilogue
+//          itself and s is the instance
 //   EMPTY: {0, 0, 0, IT_EMPTY}                 padding so each class starts on an XCD boundary
 // splits: {row, slot0, nslots, inst} finished (fixed-order sum + epilogue) by a second kernel.
 struct Schedule {
@@ -66,9 +70,10 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
                     const std::vector<Bundle> &bundles, Schedule &out);
 // Bundles of the rows of a CSR matrix: every maximal run of >= 2 consecutive rows of one
 // instance with equal length in [kBundleMinLen, kBundleMaxLen], cut into pieces of at most
-// kBundleRows rows (a last piece of one row is left out).  With col (nullable), a run also
-// needs each row's columns to be its predecessor's plus one (checked at the first, middle
-// and last entry), the pattern whose gathers a bundle coalesces.
+// kBundleRows rows (a last piece of one row is left out).  With col (nullable), a run needs
+// instead each row's columns to be its predecessor's plus one (checked at the first, middle
+// and last entry), the pattern whose gathers a bundle coalesces, and a length of at least
+// kBundleMinShifted.
 void find_bundles(int64_t rows, const int64_t *rowptr, const int32_t *col /* nullable */,
                   const int32_t *inst_of_row /* nullable */, std::vector<Bundle> &out);
 

@@ -315,9 +315,16 @@ __global__ __launch_bounds__(kWG) void k_pass(const int4 *__restrict__ items,
         S *bsum = reinterpret_cast<S *>(smem);  // [4][64]
         bsum[wv * 64 + lane] = s;
         __syncthreads();
-        if (wv == 0 && lane < R)
+        if (C == 1) {  // the whole rows: their epilogue here, lane l for row r0 + l
+            const PassCtx ctx = op.begin(it.z);
+            if (wv == 0 && lane < R && ctx.active) {
+                const S tot = ((bsum[lane] + bsum[64 + lane]) + bsum[128 + lane]) + bsum[192 + lane];
+                op.apply(it.x + lane, tot, op.load(it.x + lane), ctx, q);
+            }
+        } else if (wv == 0 && lane < R) {
             split_part[it.z + lane * C] =
                 ((bsum[lane] + bsum[64 + lane]) + bsum[128 + lane]) + bsum[192 + lane];
+        }
     }  // IT_EMPTY: padding item, only the (zero) check partials below
     if constexpr (Op::NQ > 0) {
 #pragma unroll

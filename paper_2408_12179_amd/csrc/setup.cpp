@@ -185,10 +185,11 @@ void find_bundles(int64_t rows, const int64_t *rowptr, const int32_t *col,
             if ((int64_t)col[rowptr[b] + k] != (int64_t)col[rowptr[a] + k] + 1) return false;
         return true;
     };
+    const int64_t min_len = col ? kBundleMinShifted : kBundleMinLen;
     for (int64_t r = 0; r < rows;) {
         const int64_t L = len(r);
         int64_t e = r + 1;
-        if (L >= kBundleMinLen && L <= kBundleMaxLen && inst(r) >= 0)
+        if (L >= min_len && L <= kBundleMaxLen && inst(r) >= 0)
             while (e < rows && len(e) == L && inst(e) == inst(r) && (!col || shifted(e - 1, e, L)))
                 ++e;
         for (int64_t b = r; e - b >= 2; b += kBundleRows)
@@ -226,7 +227,11 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
             const Bundle bd = bundles[nb++];
             close_tile(r);
             r0 = r + bd.R;
-            if (inst(r) >= 0) {
+            if (inst(r) >= 0 && len <= kBundleK) {  // one item, epilogue in the item
+                bitems.push_back(make_int4((int)r, (int)rowptr[r], inst(r),
+                                           (1 << 17) | ((int)(len - 1) << 9) |
+                                               ((bd.R - 1) << kKindBits) | IT_BUNDLE));
+            } else if (inst(r) >= 0) {
                 const int C = (int)((len + kBundleK - 1) / kBundleK);
                 const int s0 = out.n_chunk_slots;
                 for (int c = 0; c < C; ++c) {

@@ -61,7 +61,8 @@ def test_default_finds_shifted_rows(name):
     s = hprlp.Solver(lp, max_iter=100, lambda_override=ref.lam)
     sol = s.solve()
     sa, st = s.schedule(0), s.schedule(1)
-    assert sa["bundle_items"] > 0 and st["bundle_items"] == 0, (sa, st)
+    assert sa["bundle_items"] == expected_shifted_bundles(lp) > 0 and st["bundle_items"] == 0, \
+        (sa, st)
     check(iterates(s, sol, ref))
     s.close()
     s0 = hprlp.Solver(lp, max_iter=100, lambda_override=ref.lam, bundle_rows=0)
@@ -193,4 +194,38 @@ def test_bundle_edges(sched):
     # 64 rows x 4 items (256 = 4 * 64), 2 rows x 5 items (300), 64 + 6 rows x 5 items (257)
     assert s.schedule(0)["bundle_items"] == 4 + 5 + 5 + 5, s.schedule(0)
     check(iterates(s, s.solve(), ref))
+    s.close()
+
+
+def expected_shifted_bundles(lp, min_len=16, max_len=16384):
+    """Bundles (one work item each when rows have <= 64 entries) of the maximal runs of
+    consecutive equal-length rows whose columns are, entry by entry, the previous row's plus
+    one, cut into pieces of at most 64 rows, a last piece of one row left out."""
+    rp, ci = lp.rowptr, lp.colidx
+    lens = np.diff(rp)
+    items, r = 0, 0
+    while r < lp.m:
+        L, e = lens[r], r + 1
+        if min_len <= L <= max_len:
+            while e < lp.m and lens[e] == L and np.array_equal(
+                    ci[rp[e]:rp[e + 1]], ci[rp[e - 1]:rp[e]] + 1):
+                e += 1
+        full, rest = divmod(e - r, 64)
+        items += (full + (rest >= 2)) * -(-L // 64)
+        r = e
+    return items
+
+
+def test_short_shifted_rows_qap():
+    """QAP LP (N = 20): its 16,000 rows of N + 1 = 21 nonzeros have columns r + N^3 k, so
+    row r + 1's are row r's plus one: bundles of one work item each (21 <= 64 entries), whose
+    epilogue runs in the item, one lane per row."""
+    lp = lpgen.qap_lp(20, seed=1)
+    ref = oracle.solve(lp, max_iter=100)
+    s = hprlp.Solver(lp, max_iter=100, lambda_override=ref.lam)
+    assert s.schedule(0)["bundle_items"] == expected_shifted_bundles(lp), s.schedule(0)
+    check(iterates(s, s.solve(), ref))
+    tr = s.trace()
+    for col in ("rel_p", "rel_d", "merit"):
+        assert np.allclose(tr[:, hprlp.TRACE_COLS.index(col)], ref.trace_col(col), rtol=1e-9), col
     s.close()
