@@ -344,6 +344,16 @@ int hprlp_get_trace_instance(const hprlp_handle *h, int32_t i, double *out, long
 int hprlp_get_schedule(const hprlp_handle *h, int matrix, int32_t *params, int64_t *counts,
                        double *tuned_ms);
 
+/* The schedule hprlp_create would build for A (matrix = 0) or A^T (matrix = 1) of a single
+ * LP with m rows, n columns and the CSR (rowptr, colidx) of A (host arrays), under *opt
+ * (NULL: defaults): counts[6] as in hprlp_get_schedule (counts[4] = 0: column order is
+ * applied after create).  The options' schedule parameters are used as they are (no
+ * autotuner, which needs the GPU).  A^T's rows are A's columns after the renumbering of
+ * option reorder.  Host only: no GPU is needed.  EDIM on bad sizes, EINVAL on a bad index,
+ * row pointer or option. */
+int hprlp_plan_schedule(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                        const hprlp_options *opt, int matrix, int64_t *counts);
+
 /* Time the two iteration passes on the current state: `reps` launches of the column pass
  * (x-step over A~^T) and of the row pass (y-step over A~), each bracketed by HIP events on
  * the handle's stream.  Writes the mean duration of one launch in milliseconds.  The state

@@ -760,6 +760,29 @@ int tune_schedules(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT,
                    const int32_t *inst_row, const int32_t *inst_col);
 int set_tile_order(hprlp_handle *h, bool row, bool col, bool to_col);
 
+// Row bundles of A and A^T for options o (fixed at create): found on the caller's arrays.
+// Rows keep their order; A^T's rows are the columns, after the renumbering by decreasing
+// count when o.reorder (so its row lengths are the column counts, sorted).  rpT (nullable)
+// receives those row pointers when A^T is searched.
+void detect_bundles(const hprlp_options &o, int64_t m, int64_t n, const int64_t *rowptr,
+                    const int32_t *colidx, const int32_t *irow, const int32_t *icol,
+                    std::vector<Bundle> &bA, std::vector<Bundle> &bT,
+                    std::vector<int64_t> *rpT_out) {
+    bA.clear();
+    bT.clear();
+    if (!bundles_possible(o)) return;
+    find_bundles(m, rowptr, o.bundle_rows == 1 ? nullptr : colidx, irow, bA);
+    if (o.bundle_rows == 1) {
+        const int64_t nnz = rowptr[m];
+        std::vector<int64_t> deg((size_t)n, 0), rpT((size_t)n + 1, 0);
+        for (int64_t p = 0; p < nnz; ++p) deg[colidx[p]]++;
+        if (o.reorder) std::stable_sort(deg.begin(), deg.end(), std::greater<int64_t>());
+        for (int64_t j = 0; j < n; ++j) rpT[j + 1] = rpT[j] + deg[j];
+        find_bundles(n, rpT.data(), nullptr, icol, bT);
+        if (rpT_out) *rpT_out = std::move(rpT);
+    }
+}
+
 // Store every bundle's nonzeros k-major (once, after the preprocessing): each bundle is
 // copied to the staging buffer, then written back in its new order.
 int store_bundles(hprlp_handle *h, const int64_t *rpA, const int64_t *rpT) {
@@ -921,18 +944,8 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
         }
         return HPRLP_OK;
     };
-    // Row bundles, fixed for the handle's lifetime: found on the caller's arrays (rows keep
-    // their order; A^T's rows are the columns after the renumbering by decreasing count)
-    if (bundles_possible(o)) {
-        find_bundles(m, rowptr, o.bundle_rows == 1 ? nullptr : colidx, irow, h->A.bundles);
-        if (o.bundle_rows == 1) {
-            std::vector<int64_t> deg((size_t)n, 0), rpT((size_t)n + 1, 0);
-            for (int64_t p = 0; p < nnz; ++p) deg[colidx[p]]++;
-            if (o.reorder) std::stable_sort(deg.begin(), deg.end(), std::greater<int64_t>());
-            for (int64_t j = 0; j < n; ++j) rpT[j + 1] = rpT[j] + deg[j];
-            find_bundles(n, rpT.data(), nullptr, icol, h->T.bundles);
-        }
-    }
+    // Row bundles, fixed for the handle's lifetime
+    detect_bundles(o, m, n, rowptr, colidx, irow, icol, h->A.bundles, h->T.bundles, nullptr);
     Plan need = bound_plan(m, n, nnz, o, L.n_inst, L.batched);
     std::vector<int64_t> rpt;
     std::vector<std::array<double, 8>> cst;
@@ -1156,6 +1169,42 @@ extern "C" int hprlp_workspace_bytes(int64_t m1, int64_t m2, int64_t n, int64_t 
         if (int rc = t1_check(*opt, false, m1 + m2, m2, err)) return fail(nullptr, rc, err);
     }
     return workspace_impl(1, m1 + m2, n, nnz, opt, bytes, false);
+}
+
+extern "C" int hprlp_plan_schedule(int64_t m, int64_t n, const int64_t *rowptr,
+                                   const int32_t *colidx, const hprlp_options *opt, int matrix,
+                                   int64_t *counts) {
+    if (m < 1 || n < 1) return fail(nullptr, HPRLP_EDIM, "bad dimensions (need m, n >= 1)");
+    if (!rowptr || !colidx || !counts || (matrix != 0 && matrix != 1))
+        return fail(nullptr, HPRLP_EINVAL, "bad argument");
+    hprlp_options o;
+    if (opt) o = *opt;
+    else hprlp_default_options(&o);
+    resolve_options(o);
+    std::string err;
+    if (int rc = validate_options(o, err)) return fail(nullptr, rc, err);
+    if (rowptr[0] != 0) return fail(nullptr, HPRLP_EINVAL, "rowptr[0] must be 0");
+    for (int64_t i = 0; i < m; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return fail(nullptr, HPRLP_EINVAL, "rowptr not monotone");
+    for (int64_t p = 0; p < rowptr[m]; ++p)
+        if (colidx[p] < 0 || colidx[p] >= n) return fail(nullptr, HPRLP_EINVAL, "column index out of range");
+    std::vector<Bundle> bA, bT;
+    std::vector<int64_t> rpT;
+    detect_bundles(o, m, n, rowptr, colidx, nullptr, nullptr, bA, bT, &rpT);
+    if (matrix == 1 && rpT.empty()) {  // the column counts, in the order create uses
+        std::vector<int64_t> deg((size_t)n, 0);
+        for (int64_t p = 0; p < rowptr[m]; ++p) deg[colidx[p]]++;
+        if (o.reorder) std::stable_sort(deg.begin(), deg.end(), std::greater<int64_t>());
+        rpT.assign((size_t)n + 1, 0);
+        for (int64_t j = 0; j < n; ++j) rpT[j + 1] = rpT[j] + deg[j];
+    }
+    const ScheduleParams sp{o.tile_nnz, o.tile_rows, o.short_max, o.split_len, o.chunk_nnz};
+    Schedule S;
+    if (matrix == 0) build_schedule(m, rowptr, sp, nullptr, bA, S);
+    else build_schedule(n, rpT.data(), sp, nullptr, bT, S);
+    counts[0] = (int64_t)S.items.size(); counts[1] = S.n_tiles; counts[2] = S.n_rowitems;
+    counts[3] = S.n_chunks; counts[4] = 0; counts[5] = S.n_bundle_items;
+    return HPRLP_OK;
 }
 
 extern "C" int hprlp_workspace_bytes_batched(int32_t n_inst, int64_t m, int64_t n, int64_t nnz,

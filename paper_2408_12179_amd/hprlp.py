@@ -31,7 +31,7 @@ EXPORTS = ["hprlp_default_options", "hprlp_workspace_bytes", "hprlp_workspace_by
            "hprlp_stats",
            "hprlp_stats_instance", "hprlp_get_iterate", "hprlp_get_trace",
            "hprlp_get_trace_instance", "hprlp_get_schedule", "hprlp_begin", "hprlp_step",
-           "hprlp_time_passes", "hprlp_last_error", "hprlp_destroy"]
+           "hprlp_time_passes", "hprlp_plan_schedule", "hprlp_last_error", "hprlp_destroy"]
 
 
 class Options(C.Structure):
@@ -107,6 +107,7 @@ def load() -> C.CDLL:
     lib.hprlp_get_trace_instance.argtypes = [P, C.c_int32, P, C.c_longlong,
                                              C.POINTER(C.c_longlong)]
     lib.hprlp_get_schedule.argtypes = [P, C.c_int, P, P, C.POINTER(C.c_double)]
+    lib.hprlp_plan_schedule.argtypes = [C.c_int64, C.c_int64, P, P, P, C.c_int, P]
     lib.hprlp_solve.argtypes = [P, P, P, P, C.POINTER(C.c_int)]
     lib.hprlp_begin.argtypes = [P]
     lib.hprlp_step.argtypes = [P, C.c_int]
@@ -149,6 +150,21 @@ def workspace_bytes(m1: int, m2: int, n: int, nnz: int, opts: Options) -> int:
     if rc != OK:
         raise HPRLPError(rc, last_error())
     return int(out.value)
+
+
+def plan_schedule(lp, matrix: int, **options) -> dict:
+    """Schedule counts hprlp_create would build for A (matrix=0) or A^T (matrix=1) of lp,
+    computed on the host (no GPU)."""
+    opts = default_options(**options)
+    rowptr = np.ascontiguousarray(lp.rowptr, dtype=np.int64)
+    colidx = np.ascontiguousarray(lp.colidx, dtype=np.int32)
+    counts = np.zeros(6, dtype=np.int64)
+    rc = load().hprlp_plan_schedule(lp.m, lp.n, _ptr(rowptr), _ptr(colidx), C.byref(opts),
+                                    matrix, _ptr(counts))
+    if rc != OK:
+        raise HPRLPError(rc, last_error())
+    return dict(items=int(counts[0]), tiles=int(counts[1]), row_items=int(counts[2]),
+                chunks=int(counts[3]), bundle_items=int(counts[5]))
 
 
 def workspace_bytes_batched(n_inst: int, m: int, n: int, nnz: int, opts: Options) -> int:
