@@ -96,3 +96,40 @@ def test_plan_schedule_refusals(lib):
     with pytest.raises(hprlp.HPRLPError) as e:
         hprlp.plan_schedule(bad, 0)
     assert e.value.code == hprlp.EINVAL
+
+
+def composed_lp(seed):
+    """Rows from random segments: random short rows, shift-structured runs (columns of row
+    r + 1 = row r's plus one) and equal-length runs with random columns, of random lengths
+    (8..600) and run sizes (1..150), in a random order."""
+    rng = np.random.default_rng(seed)
+    n = 200000
+    rows = []
+    for _ in range(rng.integers(5, 15)):
+        kind = rng.integers(0, 3)
+        R = int(rng.integers(1, 150))
+        L = int(rng.choice([8, 15, 16, 17, 40, 64, 65, 200, 255, 256, 257, 600]))
+        if kind == 0:
+            rows += [np.sort(rng.choice(n, size=rng.integers(1, 30), replace=False)) for _ in range(R)]
+        elif kind == 1:
+            stride = int(rng.integers(R + 1, (n - R) // L))
+            base = int(rng.integers(0, n - R - stride * (L - 1)))
+            rows += [base + r + stride * np.arange(L) for r in range(R)]
+        else:
+            rows += [np.sort(rng.choice(n, size=L, replace=False)) for _ in range(R)]
+    rowptr = np.concatenate([[0], np.cumsum([len(c) for c in rows])]).astype(np.int64)
+    colidx = np.concatenate(rows).astype(np.int32)
+    m = len(rows)
+    return lpgen.LP("composed", m, 0, n, rowptr, colidx, np.ones(len(colidx)), np.ones(m),
+                    np.ones(n), np.zeros(n), np.full(n, 1.0))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_bundle_detection_on_composed_matrices(lib, seed):
+    lp = composed_lp(seed)
+    assert hprlp.plan_schedule(lp, 0)["bundle_items"] == expected_shifted_bundles(lp)
+    assert hprlp.plan_schedule(lp, 0, bundle_rows=1)["bundle_items"] == \
+        expected_equal_run_bundles(np.diff(lp.rowptr))
+    assert hprlp.plan_schedule(lp, 1, bundle_rows=1)["bundle_items"] == \
+        expected_equal_run_bundles(col_counts(lp))
+    assert hprlp.plan_schedule(lp, 0, bundle_rows=0)["bundle_items"] == 0
