@@ -73,6 +73,7 @@ struct T1Dev {
     double *G = nullptr;                               // [mp][mp], mp = t1_padded_rows(m)
     double *U = nullptr, *V = nullptr, *S = nullptr;   // [mp][64], [mp][64], [64][64]
     double *r = nullptr, *d0 = nullptr, *dd = nullptr; // [m], [m], [mp]
+    double *P = nullptr;    // partials of G r from G's lower triangle (large G only)
     double *parts = nullptr;                           // [t1_parts_len()]
 };
 
@@ -306,6 +307,7 @@ void carve(Carver &cv, const Plan &p, hprlp_handle *h) {
         t1.G = cv.arr<double>(mp * mp);
         t1.U = cv.arr<double>(mp * 64); t1.V = cv.arr<double>(mp * 64); t1.S = cv.arr<double>(64 * 64);
         t1.r = cv.arr<double>(m); t1.d0 = cv.arr<double>(m); t1.dd = cv.arr<double>(mp);
+        if (t1_partials_len((int)p.t1m) > 0) t1.P = cv.arr<double>(t1_partials_len((int)p.t1m));
         t1.parts = cv.arr<double>(t1_parts_len());
     }
     int *bund_ci = nullptr;
@@ -1356,7 +1358,8 @@ struct ProfRec {
 hipError_t row_step(hprlp_handle *h, bool keep, const IterScalars &s, const void *vs,
                     hipEvent_t em) {
     if (!h->opt.t1_zero) return launch_row_pass(h->prec, keep, h->A, vs, s, h->st, em);
-    hipError_t e = t1_row_step(h->A, h->v64, s, h->t1.G, h->t1.r, (int)h->m, keep, h->st);
+    hipError_t e = t1_row_step(h->A, h->v64, s, h->t1.G, h->t1.r, h->t1.P, (int)h->m, keep,
+                               h->st);
     if (e == hipSuccess && em) e = hipEventRecord(em, h->st);
     return e;
 }

@@ -294,6 +294,10 @@ constexpr int kT1MaxRows = 65536;  // G takes 8 mp^2 bytes (34 GB at this bound)
 size_t t1_parts_len();
 // rows of the padded dense arrays: m rounded up to the 64-wide panels
 int t1_padded_rows(int m);
+// G r from G's lower triangle (when G exceeds 1 GiB): t1_partials_len(m) doubles of
+// partials (0 otherwise)
+bool t1_lower_product(int m);
+size_t t1_partials_len(int m);
 // G = (A~A~^T)^{-1} in place in F ([mp][mp], mp = t1_padded_rows(m); G's rows have stride
 // mp), by a blocked symmetric sweep; U, V: [mp][64] and Sb: [64][64] scratch; diag0 [m]: the
 // diagonal of A~A~^T; diagd [mp]: its LDL^T pivots (for the rank check on the host)
@@ -303,9 +307,11 @@ hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, 
 // r = b~ - A~ x_hat through the pass kernel and A's schedule (kernels.hip)
 hipError_t launch_t1_resid(const DevMat &A, const double *xhat, const double *bd, double *r,
                            hipStream_t st);
-// y-step: r = b~ - A~ x_hat, then y_bar = y + (G r) / sigma and the y update of Algorithm 2
+// y-step: r = b~ - A~ x_hat, then y_bar = y + (G r) / sigma and the y update of Algorithm 2;
+// P (nullable): the partials of the lower-triangle product
 hipError_t t1_row_step(const DevMat &A, const VecSet<double> &v, const IterScalars &s,
-                       const double *G, double *r, int m, bool keep, hipStream_t st);
+                       const double *G, double *r, double *P, int m, bool keep,
+                       hipStream_t st);
 // *out = ||A~^T (va - vb)||^2 (vb nullable); parts: t1_parts_len() doubles
 hipError_t t1_atv_sq(const DevMat &T, int n, const double *va, const double *vb, double *parts,
                      double *out, hipStream_t st);

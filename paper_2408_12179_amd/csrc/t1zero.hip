@@ -320,6 +320,71 @@ __global__ __launch_bounds__(kT) void k_t1_solve(const double *__restrict__ G,
     }
 }
 
+// G r from the lower triangle of G only (G beyond the infinity cache): lower tile (I, K)
+// (blockIdx.x enumerates the lower tiles) gives the row partials G_IK r_K -> P[I0 + a][K]
+// and, for K < I, the column partials (G_IK)^T r_I = G_KI r_I -> P[K0 + b][I].  Wavefront
+// w takes the tile's rows a = w + 4j (j < 16, in order), lane b its column b; every
+// partial has a fixed order (the row partial a butterfly over the lanes, the column
+// partial the rows of each wavefront, then the four wavefronts in order).
+__global__ __launch_bounds__(kT) void k_t1_gr_tiles(const double *__restrict__ G,
+                                                    const double *__restrict__ r, int m,
+                                                    int mp, int nbk, double *__restrict__ P) {
+    int I, K;
+    lower_tile(blockIdx.x, I, K);
+    const int I0 = I * kB, K0 = K * kB, t = threadIdx.x, w = t >> 6, b = t & 63;
+    __shared__ double colp[4][kB];
+    const double rk = K0 + b < m ? r[K0 + b] : 0.0;
+    double cacc = 0.0;
+    for (int j = 0; j < kB / 4; ++j) {
+        const int a = w + 4 * j;
+        const double g = G[(int64_t)(I0 + a) * mp + K0 + b];
+        const double ra = I0 + a < m ? r[I0 + a] : 0.0;
+        const double s = wave_sum(g * rk);
+        if (b == 0) P[(int64_t)(I0 + a) * nbk + K] = s;
+        cacc += g * ra;
+    }
+    if (K < I) {
+        colp[w][b] = cacc;
+        __syncthreads();
+        if (w == 0)
+            P[(int64_t)(K0 + b) * nbk + I] = ((colp[0][b] + colp[1][b]) + colp[2][b]) + colp[3][b];
+    }
+}
+
+// The y-step after k_t1_gr_tiles: (G r)_i = the sum of row i's nbk partials in block order,
+// then the y update of Algorithm 2 as in k_t1_solve.
+__global__ __launch_bounds__(kT) void k_t1_solve_p(const double *__restrict__ P, int nbk, int m,
+                                                   double *__restrict__ y,
+                                                   const double *__restrict__ y0,
+                                                   double *__restrict__ ybar,
+                                                   double *__restrict__ dy, IterScalars s,
+                                                   int keep) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (i >= m) return;
+    const double *Pi = P + (int64_t)i * nbk;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+    int k = lane;
+    for (; k + 192 < nbk; k += 256) {
+        d0 += Pi[k];
+        d1 += Pi[k + 64];
+        d2 += Pi[k + 128];
+        d3 += Pi[k + 192];
+    }
+    for (; k < nbk; k += 64) d0 += Pi[k];
+    const double d = wave_sum((d0 + d1) + (d2 + d3));
+    if (lane != 0) return;
+    const double yi = y[i];
+    double yb = yi + d / s.sigma;
+    if (i >= s.m1) yb = yb > 0.0 ? yb : 0.0;
+    const double yr = s.rho == 2.0 ? 2.0 * yb - yi : s.rho * yb + (1.0 - s.rho) * yi;
+    y[i] = s.hy0 * y0[i] + s.hy1 * yr;
+    if (keep) {
+        ybar[i] = yb;
+        dy[i] = yi - yr;
+    }
+}
+
 // parts[block] = sum over the block's columns j of (A~^T (va - vb))_j^2 (vb nullable);
 // a fixed grid walks the columns in a fixed order
 constexpr int kAtvBlocks = 1024;
@@ -370,6 +435,16 @@ size_t t1_parts_len() { return kAtvBlocks; }
 
 int t1_padded_rows(int m) { return (m + kB - 1) / kB * kB; }
 
+bool t1_lower_product(int m) {
+    const size_t mp = (size_t)t1_padded_rows(m);
+    return mp * mp * sizeof(double) > ((size_t)1 << 30);
+}
+
+size_t t1_partials_len(int m) {
+    const size_t mp = (size_t)t1_padded_rows(m);
+    return t1_lower_product(m) ? mp * (mp / kB) : 0;
+}
+
 hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, double *U,
                             double *V, double *Sb, double *diag0, double *diagd,
                             hipStream_t st) {
@@ -395,13 +470,21 @@ hipError_t t1_build_inverse(const DevMat &A, const DevMat &T, int m, double *F, 
 }
 
 hipError_t t1_row_step(const DevMat &A, const VecSet<double> &v, const IterScalars &s,
-                       const double *G, double *r, int m, bool keep, hipStream_t st) {
+                       const double *G, double *r, double *P, int m, bool keep,
+                       hipStream_t st) {
     const int nb = (m + kT / 64 - 1) / (kT / 64);
     hipError_t e = launch_t1_resid(A, v.xhat, v.bd, r, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_t1_solve, dim3(nb), dim3(kT), 0, st, G, r, m, t1_padded_rows(m), v.y,
-                       v.y0, v.ybar,
-                       v.dy, s, keep ? 1 : 0);
+    if (P) {
+        const int nbk = t1_padded_rows(m) / kB;
+        hipLaunchKernelGGL(k_t1_gr_tiles, dim3(nbk * (nbk + 1) / 2), dim3(kT), 0, st, G, r, m,
+                           t1_padded_rows(m), nbk, P);
+        hipLaunchKernelGGL(k_t1_solve_p, dim3(nb), dim3(kT), 0, st, P, nbk, m, v.y, v.y0,
+                           v.ybar, v.dy, s, keep ? 1 : 0);
+    } else {
+        hipLaunchKernelGGL(k_t1_solve, dim3(nb), dim3(kT), 0, st, G, r, m, t1_padded_rows(m),
+                           v.y, v.y0, v.ybar, v.dy, s, keep ? 1 : 0);
+    }
     return hipGetLastError();
 }
 
