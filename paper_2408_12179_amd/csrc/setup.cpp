@@ -37,20 +37,31 @@ int validate_problem(int64_t m1, int64_t m2, int64_t n, const int64_t *rowptr,
         err = "nnz must be in [1, 2^31) (A must be non-zero)";
         return HPRLP_EDIM;
     }
-    std::vector<int64_t> seen((size_t)n, -1);
-    for (int64_t i = 0; i < m; ++i)
+    // A row whose columns strictly increase repeats none; only the other rows are checked
+    // through a per-column marker (allocated on first need: a random access per nonzero
+    // into an n-entry array is what this pass would otherwise cost).
+    std::vector<int64_t> seen;
+    for (int64_t i = 0; i < m; ++i) {
+        bool increasing = true;
         for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
             const int32_t j = colidx[p];
             if (j < 0 || j >= n) {
                 err = "column index out of range in row " + std::to_string(i);
                 return HPRLP_EDIM;
             }
+            if (p > rowptr[i] && j <= colidx[p - 1]) increasing = false;
+        }
+        if (increasing) continue;
+        if (seen.empty()) seen.assign((size_t)n, -1);
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const int32_t j = colidx[p];
             if (seen[j] == i) {
                 err = "repeated column index in row " + std::to_string(i);
                 return HPRLP_EDIM;
             }
             seen[j] = i;
         }
+    }
     for (int64_t p = 0; p < nnz; ++p)
         if (!std::isfinite(val[p])) {
             err = "non-finite matrix value";

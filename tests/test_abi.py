@@ -149,6 +149,23 @@ def test_create_rejects_bad_input_before_any_gpu_call(lib, case, code):
     assert msg
 
 
+def test_repeated_columns_in_unsorted_rows(lib):
+    # rows whose columns strictly increase skip the marker check; an unsorted row goes
+    # through it: a repeat there is refused, an unsorted row without one is accepted (the
+    # misaligned workspace is then the first thing create refuses)
+    def permute_row(p, repeat):
+        a, e = p.rowptr[3], p.rowptr[4]
+        assert e - a >= 3
+        cols = p.colidx[a:e][::-1].copy()          # reversed: not increasing
+        if repeat:
+            cols[-1] = cols[0]                     # first and last entry, not adjacent
+        p.colidx[a:e] = cols
+    rc, msg = _create(lib, _bad(lambda p: permute_row(p, True)), ws=256)
+    assert rc == hprlp.EDIM and "repeated column" in msg, (rc, msg)
+    rc, msg = _create(lib, _bad(lambda p: permute_row(p, False)), ws=257)
+    assert rc == hprlp.EINVAL and "workspace" in msg, (rc, msg)
+
+
 def test_null_out_pointer(lib):
     o = hprlp.default_options()
     rc = lib.hprlp_create(None, 1, 0, 1, None, None, None, None, None, None, None, C.byref(o),
