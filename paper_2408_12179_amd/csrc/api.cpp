@@ -151,8 +151,6 @@ struct hprlp_handle {
     ScheduleParams spA{}, spT{};
     double tuned_ms[2] = {0.0, 0.0};          // autotuner: best row / column pass time
     // schedules over the instances still iterating (rebuilt as instances stop)
-    std::vector<int64_t> rpA, rpT;            // host row pointers of A and A^T
-    std::vector<int32_t> inst_row, inst_col;  // instance of every row and column
     std::vector<int64_t> inst_nnz;            // nonzeros of every instance
     int capA[3] = {0, 0, 0}, capT[3] = {0, 0, 0};  // carved items, splits, chunk slots
     int64_t sched_nnz = 0;                    // nonzeros covered by the current schedules
@@ -1062,11 +1060,9 @@ int create_impl(hprlp_handle **out, const Layout &L, const int64_t *rowptr,
         hprlp_destroy(h);
         return rc;
     }
-    if (L.batched) {  // kept to rebuild the schedules over the instances still iterating
-        h->rpA.assign(rowptr, rowptr + m + 1);
-        h->rpT = std::move(rpt);
-        h->inst_row = std::move(inst_row);
-        h->inst_col = std::move(inst_col);
+    if (L.batched) {  // kept to filter the schedules to the instances still iterating
+        h->A.full = h->A.host;
+        h->T.full = h->T.host;
         h->inst_nnz.assign(L.n_inst, 0);
         for (int bi = 0; bi < L.n_inst; ++bi)
             h->inst_nnz[bi] = rowptr[L.row_off[bi + 1]] - rowptr[L.row_off[bi]];
@@ -2068,22 +2064,20 @@ int solve_single(hprlp_handle *h, double *x, double *y, double *z, int *status) 
 // in the full schedule (tiles never straddle instances), so the result fits the carved
 // arrays; stopped instances simply have no work item left.
 int set_schedules(hprlp_handle *h, const std::vector<int> &keep) {
-    std::vector<int32_t> ir, ic;
     int64_t nnz = h->nnz;
     if (!keep.empty()) {
-        ir = h->inst_row;
-        ic = h->inst_col;
-        for (auto &v : ir) v = keep[v] ? v : -1;
-        for (auto &v : ic) v = keep[v] ? v : -1;
         nnz = 0;
         for (int b = 0; b < h->n_inst; ++b)
             if (keep[b]) nnz += h->inst_nnz[b];
     }
     Schedule sa, stt;
-    build_schedule(h->m, h->rpA.data(), h->spA, keep.empty() ? h->inst_row.data() : ir.data(),
-                   h->A.bundles, sa);
-    build_schedule(h->n, h->rpT.data(), h->spT, keep.empty() ? h->inst_col.data() : ic.data(),
-                   h->T.bundles, stt);
+    if (keep.empty()) {
+        sa = h->A.full;
+        stt = h->T.full;
+    } else {
+        filter_schedule(h->A.full, keep, sa);
+        filter_schedule(h->T.full, keep, stt);
+    }
     if ((int)sa.items.size() > h->capA[0] || (int)sa.splits.size() > h->capA[1] ||
         sa.n_chunk_slots > h->capA[2] || (int)stt.items.size() > h->capT[0] ||
         (int)stt.splits.size() > h->capT[1] || stt.n_chunk_slots > h->capT[2])

@@ -55,6 +55,11 @@ struct Schedule {
     int n_chunk_slots = 0;
     int tile_nnz = 0, tile_rows = 0;
     long long n_tiles = 0, n_rowitems = 0, n_chunks = 0, n_bundle_items = 0;
+    // the work items of every class before their XCD layout, with what filtering them by
+    // instance needs (a batched solve drops the instances that have stopped)
+    std::vector<int4> cls_chunks, cls_bundles, cls_long, cls_tiles;
+    std::vector<int> bundle_inst;       // instance of every bundle item
+    std::vector<int64_t> long_len;      // length of every whole-workgroup row
 };
 
 struct ScheduleParams {
@@ -68,6 +73,11 @@ struct ScheduleParams {
 void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &sp,
                     const int32_t *inst_of_row /* nullable */,
                     const std::vector<Bundle> &bundles, Schedule &out);
+// The schedule of the instances with keep[b] != 0 from the schedule of all of them: the
+// same work items, in the same order, as build_schedule over the kept rows (split slots
+// keep their numbers).
+void filter_schedule(const Schedule &full, const std::vector<int> &keep, Schedule &out);
+
 // Bundles of the rows of a CSR matrix: every maximal run of >= 2 consecutive rows of one
 // instance with equal length in [kBundleMinLen, kBundleMaxLen], cut into pieces of at most
 // kBundleRows rows (a last piece of one row is left out).  With col (nullable), a run needs
@@ -97,6 +107,7 @@ struct DevMat {
     bool sorted = false;
     // row bundles (fixed at create; their nonzeros are stored k-major from then on)
     std::vector<Bundle> bundles;
+    Schedule full;              // batched: the schedule of every instance
 };
 // Store the nonzeros [P0, P0 + R L) of one bundle k-major, from their row-major copy in
 // (tci, tva); values are float (mat_f32) or double.

@@ -209,6 +209,69 @@ void find_bundles(int64_t rows, const int64_t *rowptr, const int32_t *col,
     }
 }
 
+// The XCD layout of a schedule's classes into its work-item list.  Heaviest work first so
+// the tail of the launch is made of small tiles.  Each class is padded to a multiple of kXCD
+// and interleaved: workgroup b runs on XCD b % kXCD, so the item at position kXCD*k + x of
+// a class segment is item x*q + k of the class (q = padded length / kXCD): XCD x walks the
+// contiguous range [x*q, (x+1)*q).  Whole-workgroup rows are sorted by decreasing length:
+// contiguous ranges of a mixed-length list would give the first XCD all the heavy rows.
+// Runs of equal length that fill every XCD many times over (e.g. the supply and the demand
+// rows of a transportation LP) are range-interleaved; the rest is dealt round-robin, which
+// keeps the XCD shares equal.
+static void assemble_schedule(Schedule &out) {
+    out.items.clear();
+    auto append = [&](const std::vector<int4> &src, size_t a, size_t e) {
+        if (e <= a) return;
+        std::vector<int4> cls(src.begin() + a, src.begin() + e);
+        while (cls.size() % kXCD) cls.push_back(make_int4(0, 0, 0, IT_EMPTY));
+        const size_t q = cls.size() / kXCD;
+        for (size_t k = 0; k < q; ++k)
+            for (int x = 0; x < kXCD; ++x) out.items.push_back(cls[x * q + k]);
+    };
+    const std::vector<int4> &lr = out.cls_long;
+    out.items.reserve(out.cls_chunks.size() + out.cls_bundles.size() + lr.size() +
+                      out.cls_tiles.size() + 5 * kXCD + lr.size());
+    append(out.cls_chunks, 0, out.cls_chunks.size());
+    append(out.cls_bundles, 0, out.cls_bundles.size());
+    for (size_t a = 0; a < lr.size();) {
+        size_t e = a;
+        while (e < lr.size() && out.long_len[e] == out.long_len[a]) ++e;
+        if (e - a >= (size_t)(16 * kXCD)) append(lr, a, e);
+        else out.items.insert(out.items.end(), lr.begin() + a, lr.begin() + e);
+        a = e;
+    }
+    append(out.cls_tiles, 0, out.cls_tiles.size());
+    out.n_tiles = (long long)out.cls_tiles.size();
+    out.n_rowitems = (long long)lr.size();
+    out.n_chunks = (long long)out.cls_chunks.size();
+    out.n_bundle_items = (long long)out.cls_bundles.size();
+}
+
+void filter_schedule(const Schedule &full, const std::vector<int> &keep, Schedule &out) {
+    out = Schedule{};
+    out.tile_nnz = full.tile_nnz;
+    out.tile_rows = full.tile_rows;
+    out.n_chunk_slots = full.n_chunk_slots;
+    auto kept = [&](int b) { return b >= 0 && keep[(size_t)b] != 0; };
+    for (const int4 &it : full.cls_chunks)
+        if (kept(it.z)) out.cls_chunks.push_back(it);
+    for (size_t i = 0; i < full.cls_bundles.size(); ++i)
+        if (kept(full.bundle_inst[i])) {
+            out.cls_bundles.push_back(full.cls_bundles[i]);
+            out.bundle_inst.push_back(full.bundle_inst[i]);
+        }
+    for (size_t i = 0; i < full.cls_long.size(); ++i)
+        if (kept(full.cls_long[i].w >> kKindBits)) {
+            out.cls_long.push_back(full.cls_long[i]);
+            out.long_len.push_back(full.long_len[i]);
+        }
+    for (const int4 &it : full.cls_tiles)
+        if (kept(it.z)) out.cls_tiles.push_back(it);
+    for (const int4 &sp : full.splits)
+        if (kept(sp.w)) out.splits.push_back(sp);
+    assemble_schedule(out);
+}
+
 void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &sp,
                     const int32_t *inst_of_row, const std::vector<Bundle> &bundles,
                     Schedule &out) {
@@ -218,6 +281,8 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
     out.tile_nnz = sp.tile_nnz;
     out.tile_rows = sp.tile_rows;
     out.n_bundle_items = 0;
+    out.bundle_inst.clear();
+    out.long_len.clear();
     std::vector<int4> tiles, longrows, chunks, bitems;
     std::vector<std::pair<int64_t, int64_t>> longlen;  // (len, row) for ordering
     auto inst = [&](int64_t r) { return inst_of_row ? inst_of_row[r] : 0; };
@@ -242,6 +307,7 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
                 bitems.push_back(make_int4((int)r, (int)rowptr[r], inst(r),
                                            (1 << 17) | ((int)(len - 1) << 9) |
                                                ((bd.R - 1) << kKindBits) | IT_BUNDLE));
+                out.bundle_inst.push_back(inst(r));
             } else if (inst(r) >= 0) {
                 const int C = (int)((len + kBundleK - 1) / kBundleK);
                 const int s0 = out.n_chunk_slots;
@@ -250,6 +316,7 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
                     bitems.push_back(make_int4((int)r, (int)(rowptr[r] + (int64_t)c * kBundleK * bd.R),
                                                s0 + c, (C << 17) | ((kn - 1) << 9) |
                                                            ((bd.R - 1) << kKindBits) | IT_BUNDLE));
+                    out.bundle_inst.push_back(inst(r));
                 }
                 for (int l = 0; l < bd.R; ++l)
                     out.splits.push_back(make_int4((int)r + l, s0 + l * C, C, inst(r)));
@@ -289,42 +356,17 @@ void build_schedule(int64_t rows, const int64_t *rowptr, const ScheduleParams &s
     std::stable_sort(longlen.begin(), longlen.end(),
                      [](const std::pair<int64_t, int64_t> &a,
                         const std::pair<int64_t, int64_t> &b) { return a.first > b.first; });
-    for (auto &lr : longlen)
+    for (auto &lr : longlen) {
         longrows.push_back(make_int4((int)lr.second, (int)rowptr[lr.second],
                                      (int)rowptr[lr.second + 1],
                                      (inst(lr.second) << kKindBits) | IT_ROW));
-    // Heaviest work first so the tail of the launch is made of small tiles.  Each class is
-    // padded to a multiple of kXCD and interleaved: workgroup b runs on XCD b % kXCD, so the
-    // item at position kXCD*k + x of a class segment is item x*q + k of the class (q = padded
-    // length / kXCD): XCD x walks the contiguous range [x*q, (x+1)*q).
-    auto append = [&](std::vector<int4> &cls) {
-        if (cls.empty()) return;
-        while (cls.size() % kXCD) cls.push_back(make_int4(0, 0, 0, IT_EMPTY));
-        const size_t q = cls.size() / kXCD;
-        for (size_t k = 0; k < q; ++k)
-            for (int x = 0; x < kXCD; ++x) out.items.push_back(cls[x * q + k]);
-    };
-    // Whole-workgroup rows are sorted by decreasing length: contiguous ranges of a mixed-length
-    // list would give the first XCD all the heavy rows.  Runs of equal length that fill every
-    // XCD many times over (e.g. the supply and the demand rows of a transportation LP) are
-    // range-interleaved; the rest is dealt round-robin, which keeps the XCD shares equal.
-    out.items.reserve(chunks.size() + bitems.size() + longrows.size() + tiles.size() + 5 * kXCD +
-                      longlen.size());
-    append(chunks);
-    out.n_bundle_items = (long long)bitems.size();
-    append(bitems);
-    for (size_t a = 0; a < longrows.size();) {
-        size_t e = a;
-        while (e < longrows.size() && longlen[e].first == longlen[a].first) ++e;
-        std::vector<int4> run(longrows.begin() + a, longrows.begin() + e);
-        if (run.size() >= (size_t)(16 * kXCD)) append(run);
-        else out.items.insert(out.items.end(), run.begin(), run.end());
-        a = e;
+        out.long_len.push_back(lr.first);
     }
-    append(tiles);
-    out.n_tiles = (long long)tiles.size();
-    out.n_rowitems = (long long)longrows.size();
-    out.n_chunks = (long long)chunks.size();
+    out.cls_chunks = std::move(chunks);
+    out.cls_bundles = std::move(bitems);
+    out.cls_long = std::move(longrows);
+    out.cls_tiles = std::move(tiles);
+    assemble_schedule(out);
 }
 
 }  // namespace hprlp
